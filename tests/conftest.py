@@ -1,0 +1,23 @@
+"""Shared pytest set-up: markers, import path and the oracle/library builds."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    """The FP64 oracle (built with gcc on first use if no build is present)."""
+    import oracle
+
+    oracle.lib()
+    return oracle
