@@ -1,0 +1,199 @@
+"""Benchmark: PSO force-inversion generations on one MI355X.
+
+One step = one PSO generation of the whole hot path over the workload's swarm: RK4 integration of
+every particle's trajectory, lock-in projection and window misfit (one kernel), then personal and
+swarm bests and the Eq. 8 move (one kernel).  Steps run inside the library's captured HIP graph
+(afm_invert), inputs resident in HBM.
+
+Default workload: the precision-path configuration -- point-mass DMT cantilever (k = 40 N/m,
+f0 = 300 kHz, Q = 400, A0 = 20 nm, set-point 0.8 A0), 3 free parameters (H, E*, a0) with uniform
+priors, 1024 particles, 500 periods x 256 RK4 steps, FP32 integration with FP64 lock-in and misfit
+sums, noisy synthetic target (sigma 0.05 nm) made by the plain FP64 GPU path at the truth.
+
+Prints one JSON line (metric RK4 steps/s).  Also reported: inversions/s (200 generations per
+inversion), the plain FP64 GPU path on the same workload, the forward kernel's roofline (FP32
+VALU), the same kernel on a GPU-filling batch, and the oracle timed on one host core.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s
+# per issued FP32 instruction stream; AMD's published 157.3 TFLOP/s counts packed (2-wide) FP32,
+# which this build does not emit.  `peak` reports the published figure.
+PEAK_FP32_PUBLISHED = 157.3e12
+PEAK_FP32_SCALAR_ISSUE = 78.6e12
+# Algorithmic FP32 flops per RK4 step of the point-mass DMT kernel (FMA = 2, rcp/sqrt = 1),
+# out-of-contact force path: 4 stages x (gap 1 + force 4 + acceleration 4) + 3 stage states x 4
+# + slope sums 10 + compensated update 10.
+FLOPS_PER_STEP_DMT1 = 68
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip FP64 and saturated legs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, seconds):
+    """Oracle misfit of C2 particles, one host core, until `seconds` of work (max 200)."""
+    import numpy as np
+
+    import oracle
+
+    m = cfg["model"]
+    base = __import__("workloads").full_params(cfg)
+    U = np.sin(np.arange(m["lockin_cycles"] * m["steps_per_cycle"]) * 0.1) * 1.6e-8
+    th = __import__("workloads").draw_free(cfg, 200, 99)
+    free = __import__("workloads").free_index(cfg)
+    steps_per = m["n_cycles"] * m["steps_per_cycle"]
+    t0 = time.perf_counter()
+    n = 0
+    while n < 200:
+        p = base.copy()
+        for j, f in enumerate(free):
+            p[f[0]] = th[n, j]
+        oracle.forward(m, p, U)
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * steps_per / dt, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} particles of the workload (misfit, {m['n_cycles']} periods x "
+                      f"{m['steps_per_cycle']} steps each), FP64, single thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the inversion path has no "
+              "multi-GPU mode in this build.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1109_0334_amd as afm
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = W.config("c2")
+    m = cfg["model"]
+    P = cfg["particles"]
+    Wn = m["lockin_cycles"] * m["steps_per_cycle"]
+    steps_per_traj = m["n_cycles"] * m["steps_per_cycle"]
+    free = W.free_index(cfg)
+    p_true = W.full_params(cfg)
+
+    # target: plain FP64 GPU trace at the truth plus seeded measurement noise (setup, untimed)
+    ref = afm.Plan(m, p_true, free, precision="fp64", device=dev)
+    truth = torch.tensor([[cfg["truth"]["H"]], [cfg["truth"]["Estar"]], [cfg["truth"]["a0"]]],
+                         dtype=torch.float64, device=dev)
+    U = ref.forward_batch(truth, trace=True)["trace"] + torch.tensor(W.noise(cfg, Wn, 0), device=dev)
+    U = U.contiguous()
+
+    plan = afm.Plan(m, p_true, free, precision="mixed", device=dev)
+    K, Wu = max(1, args.steps), max(1, args.warmup)
+    plan.invert(U, P, Wu, seed=cfg["seed"], cutoff=1e-3)   # warm-up generations
+    torch.cuda.synchronize()
+    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)  # capture the K-generation graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)  # timed replay
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / K * 1e3
+    rk4_steps = P * steps_per_traj * K
+    value = rk4_steps / dt
+
+    # forward kernel alone, same launch as in the graph, timed with events on its stream
+    theta = W.draw_free(cfg, P, 5).T.copy()
+    th_dev = torch.tensor(theta, device=dev)
+    plan.misfit(th_dev, U)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, K)
+    e0.record()
+    for _ in range(reps):
+        plan.misfit(th_dev, U)
+    e1.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / reps
+    flops = FLOPS_PER_STEP_DMT1 * P * steps_per_traj
+    achieved = flops / (k_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_PUBLISHED / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": None,
+            "kernel": "k_forward<DMT,1 mode,mixed>", "kernel_ms": k_ms,
+            "flops_per_launch": flops, "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_ISSUE,
+            "occupancy": f"{P} trajectories = {P // 64} waves on 1024 SIMDs"}
+
+    extras = {}
+    if not args.no_extras:
+        # plain FP64 per-particle forward on the same workload (one generation's misfits)
+        plan64 = afm.Plan(m, p_true, free, precision="fp64", device=dev)
+        plan64.misfit(th_dev, U)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            plan64.misfit(th_dev, U)
+        e1.record()
+        torch.cuda.synchronize()
+        f64_ms = e0.elapsed_time(e1) / 3
+        extras["fp64_forward"] = {"kernel_ms": f64_ms, "rk4_steps_per_s": P * steps_per_traj / (f64_ms * 1e-3),
+                                  "mixed_speedup": f64_ms / k_ms}
+        # the same kernel on a batch that fills the GPU (4096 swarms x 128 particles, 40 periods)
+        n_sat, nc_sat = 4096 * 128, 40
+        msat = dict(m, n_cycles=nc_sat)
+        plan_sat = afm.Plan(msat, p_true, free, precision="mixed", device=dev)
+        th_sat = torch.tensor(W.draw_free(cfg, n_sat, 6).T.copy(), device=dev)
+        tid = torch.zeros(n_sat, dtype=torch.int32, device=dev)
+        plan_sat.misfit(th_sat, U, target_id=tid)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            plan_sat.misfit(th_sat, U, target_id=tid)
+        e1.record()
+        torch.cuda.synchronize()
+        sat_ms = e0.elapsed_time(e1) / 3
+        sat_steps = n_sat * nc_sat * m["steps_per_cycle"]
+        sat_ach = FLOPS_PER_STEP_DMT1 * sat_steps / (sat_ms * 1e-3)
+        extras["saturated_forward"] = {
+            "trajectories": n_sat, "periods": nc_sat, "kernel_ms": sat_ms,
+            "rk4_steps_per_s": sat_steps / (sat_ms * 1e-3), "achieved_tflops": sat_ach / 1e12,
+            "frac_published_peak": sat_ach / PEAK_FP32_PUBLISHED,
+            "frac_scalar_issue_peak": sat_ach / PEAK_FP32_SCALAR_ISSUE}
+
+    line = {
+        "metric": "RK4 steps/s", "value": value, "unit": "RK4 steps/s", "n_gpus": 1,
+        "steps": K, "warmup": Wu, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "precision": "FP32 RK4 state (compensated), FP64 lock-in and misfit sums",
+        "data": "synthetic",
+        "config": {"workload": "c2-precision-path: point-mass DMT, invert (H, E*, a0), "
+                               "1024 particles, 500 periods x 256 RK4 steps, noisy target",
+                   "particles": P, "periods": m["n_cycles"], "steps_per_period": m["steps_per_cycle"],
+                   "generations_per_inversion": cfg["iters"]},
+        "inversions_per_s": 1.0 / (ms_step * 1e-3 * cfg["iters"]),
+        "best_J_after_steps": float(out["best_J"].item()),
+        "roofline": roof,
+    }
+    line.update(extras)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * afm.h -- C ABI of the MI355X tip-sample force inversion library (libafm.so).
+ *
+ * The library solves the two problems posed in Busch, Zou, Ganapathysubramanian, "A near
+ * real-time framework for extracting tip-sample forces in dynamic atomic force microscopy"
+ * (arXiv 1109.0334):
+ *   FP (Sec. 2.2): given the cantilever, the base motion and a parameterised tip-sample force,
+ *       compute the tip deflection -- here reduced to the steady-state lock-in amplitude and
+ *       phase and to the misfit against a measured trace;
+ *   IP (Sec. 2.3): given the measured deflection, find the force parameters, posed as the
+ *       unconstrained minimisation of a misfit J (Eq. 5) and solved with particle swarm
+ *       optimisation (Sec. 3.4, Eq. 8).
+ *
+ * Model (Eq. 1-2 reduced to tip-normalised modes):
+ *   u = sum_i q_i,  d = z_c + u (tip-sample gap, u positive away from the sample),
+ *   q_i'' + (w_i/Q_i) q_i' + w_i^2 q_i = F(d, d'; theta) / M + gamma_i a wd^2 sin(wd t),
+ * M = k / w_0^2, base motion y_b = a sin(wd t) (Eq. 9) with a set so that the free tip amplitude
+ * is A0.  Classical RK4 with N steps per drive period (Sec. 3.2), n_cycles periods.  Lock-in over
+ * the last lockin_cycles periods: X = 2/W sum u cos(2 pi p/N), Y = 2/W sum u sin(2 pi p/N),
+ * A = sqrt(X^2 + Y^2), phi = atan2(-X, Y) (u ~ A sin(wd t - phi)).  Misfit over the same window:
+ * J = sum (U - u)^2 / sum U^2 (Eq. 5 on the steady-state window, normalised so that sqrt(J) is
+ * the relative L2 error of Sec. 3.3).
+ *
+ * Conventions for every entry point:
+ *   - SI units (m, s, N, Pa, J); phases in radians; J dimensionless.
+ *   - Array arguments are device pointers owned by the caller (e.g. torch tensor storage),
+ *     structure-of-arrays: a [D][n] array holds row j at offset j*n.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the legacy default stream).
+ *     Arguments are validated before anything is enqueued; an invalid call returns
+ *     AFM_ERR_INVALID and launches nothing.  A HIP failure returns AFM_ERR_HIP.  The text of the
+ *     last error of the calling thread is returned by afm_last_error().
+ *   - A trajectory that becomes non-finite or exceeds |u| > div_limit * A0 at the end of a drive
+ *     period is not an error: its status word gets AFM_ST_NONFINITE / AFM_ST_DIVERGED, its
+ *     amplitude and phase are NaN and its misfit +inf.
+ *   - A plan is not thread-safe: use one plan per host thread.
+ */
+#ifndef AFM_H
+#define AFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AFM_MAX_MODES 4
+#define AFM_MAX_PARAMS 8
+
+typedef void *afm_stream_t; /* a hipStream_t */
+
+typedef enum {
+    AFM_OK = 0,
+    AFM_ERR_INVALID = 1,     /* bad argument; nothing was enqueued           */
+    AFM_ERR_HIP = 2,         /* HIP runtime failure (launch, copy, capture)  */
+    AFM_ERR_NOMEM = 3,       /* device or host allocation failed             */
+    AFM_ERR_UNSUPPORTED = 4  /* valid request this build does not implement  */
+} afm_status;
+
+/* Arithmetic of the forward solve. */
+enum {
+    AFM_PREC_MIXED = 0, /* FP32 state and RK4 (compensated update), FP64 lock-in and misfit sums */
+    AFM_PREC_FP64 = 1   /* plain FP64 throughout: the per-particle baseline                      */
+};
+
+/* Tip-sample force laws F(d, d'), F > 0 repulsive.  params[] layouts (z_c always first):
+ *   DMT   {z_c, H, E*, a0, R}: -H R/(6 d^2) for d > a0; -H R/(6 a0^2) + 4/3 E* sqrt(R)
+ *         (a0 - d)^{3/2} for d <= a0 (Hertz contact with van der Waals adhesion; the paper names
+ *         Hertz and van der Waals forces in Sec. 2.2 and adhesion as an extension in Sec. 5).
+ *   LJ    {z_c, eps, r0, n, m}: eps n m/(n - m)/d [(r0/d)^n - (r0/d)^m] (Lennard-Jones type, well
+ *         depth eps at d = r0); d <= 0 yields a non-finite trajectory.
+ *   KV    {z_c, H, E*, a0, R, eta}: DMT plus -eta sqrt(R (a0 - d)) d' in contact (Kelvin-Voigt
+ *         dissipation, the spring-damper of Eq. 4 / Eq. 12 applied to a Hertzian contact).
+ *   HOOKE {z_c, k_s}: -k_s d for d < 0 (Eq. 3 / Eq. 11).
+ *   SD    {z_c, k_s, zeta_s}: -k_s d - zeta_s d' for d < 0 (Eq. 4 / Eq. 12).
+ *   NONE  {z_c}: no tip force (the linear driven cantilever).                                  */
+enum { AFM_LAW_DMT = 0, AFM_LAW_LJ = 1, AFM_LAW_KV = 2, AFM_LAW_HOOKE = 3, AFM_LAW_SD = 4,
+       AFM_LAW_NONE = 5 };
+
+/* Initial state: FREE_STEADY = linear free steady state at t = 0 (q_i = Im(a H_i),
+ * q_i' = wd Re(a H_i), H_i = gamma_i wd^2 / (w_i^2 - wd^2 + i w_i wd / Q_i)); REST = zero. */
+enum { AFM_IC_FREE_STEADY = 0, AFM_IC_REST = 1 };
+
+/* Per-trajectory status bits.  BAD_INPUT: the trajectory's target row is outside
+ * [0, n_targets) or its period count is below lockin_cycles; it is not integrated. */
+enum { AFM_ST_NONFINITE = 1, AFM_ST_DIVERGED = 2, AFM_ST_BAD_INPUT = 4 };
+
+/* Problem description, copied by value into a plan (FP: Sec. 2.2; IP search box: Sec. 3.4). */
+typedef struct afm_problem {
+    int32_t n_modes;         /* 1 (point mass) .. AFM_MAX_MODES tip-normalised modes          */
+    int32_t law;             /* AFM_LAW_*                                                     */
+    int32_t steps_per_cycle; /* N, RK4 steps per drive period, 4 .. 4096                      */
+    int32_t n_cycles;        /* drive periods integrated (default per trajectory)             */
+    int32_t lockin_cycles;   /* periods at the end used for lock-in and misfit, >= 1          */
+    int32_t ic;              /* AFM_IC_*                                                      */
+    double k;                /* first-mode stiffness, N/m                                     */
+    double f0;               /* first-mode natural frequency, Hz                              */
+    double drive_freq;       /* base drive frequency, Hz                                      */
+    double free_amplitude;   /* A0, m; fixes the base amplitude                               */
+    double div_limit;        /* divergence threshold in units of A0 (0 => 100)                */
+    double q[AFM_MAX_MODES];     /* quality factor per mode                                   */
+    double ratio[AFM_MAX_MODES]; /* w_i / w_0 (ratio[0] is normally 1)                        */
+    double gain[AFM_MAX_MODES];  /* gamma_i, base-drive participation (1 for a point mass)    */
+    double params[AFM_MAX_PARAMS];      /* full law parameter vector, SI; free entries are
+                                           overwritten per trajectory by theta               */
+    int32_t n_free;                     /* D: free parameters, 1 .. AFM_MAX_PARAMS            */
+    int32_t free_index[AFM_MAX_PARAMS]; /* params[] slot of free parameter j                  */
+    double lo[AFM_MAX_PARAMS];          /* search box of free parameter j (SI)                */
+    double hi[AFM_MAX_PARAMS];
+    int32_t log_scale[AFM_MAX_PARAMS];  /* 1: theta = lo (hi/lo)^z, else lo + z (hi - lo)      */
+    double pso_w, pso_c1, pso_c2, pso_vmax; /* Eq. 8 weights; 0 => 0.7298, 1.49618, 1.49618, 1 */
+} afm_problem;
+
+typedef struct afm_plan afm_plan; /* opaque: constants, drive/lock-in tables, workspace */
+
+/* Swarm state, caller-owned device arrays in normalised coordinates z in [0,1]^D for S swarms
+ * of P particles (particle g = s*P + p).  theta receives the SI parameters of the positions. */
+typedef struct afm_swarm {
+    int32_t n_dim, particles, swarms;
+    double *z, *v, *pbest_z; /* [D][S*P] */
+    double *pbest_J;         /* [S*P]    */
+    double *gbest_z;         /* [D][S]   */
+    double *gbest_J;         /* [S]      */
+    int32_t *gen_to_cutoff;  /* [S]: first generation with sqrt(gbest_J) <= cutoff, or -1   */
+    double *theta;           /* [D][S*P]: SI parameters of z (written by init and step)      */
+} afm_swarm;
+
+/* Build a plan: validates the problem, derives the base amplitude, initial state and the
+ * non-dimensional constants, uploads the drive and lock-in tables.  precision: AFM_PREC_*.
+ * Allocates device memory owned by the plan.  *out is NULL on failure. */
+afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_plan **out);
+
+/* Release a plan and its device memory (synchronises the plan's private stream).  NULL is OK. */
+afm_status afm_plan_destroy(afm_plan *plan);
+
+/* FP for n parameter points.  theta: [n_free][n] SI values of the free parameters (device).
+ * n_cycles: [n] per-trajectory period counts, or NULL for the problem's n_cycles (each must be
+ * >= lockin_cycles).  Outputs (device): amp [n] in m, phase [n] in rad, status [n]; trace, if
+ * not NULL, [n][W] FP64 window deflection in m, W = lockin_cycles * steps_per_cycle. */
+afm_status afm_forward_batch(afm_plan *plan, int64_t n, const double *theta,
+                             const int32_t *n_cycles, double *amp, double *phase, double *trace,
+                             int32_t *status, afm_stream_t stream);
+
+/* Misfit J (Eq. 5 on the lock-in window, normalised) of n parameter points against measured
+ * traces.  targets: [n_targets][W] FP64 deflections in m on the window samples (the states after
+ * steps N_tot - W + 1 .. N_tot); target_id: [n] row of targets per point, or NULL for row 0
+ * (rows outside [0, n_targets) give status AFM_ST_BAD_INPUT).
+ * Outputs (device): J [n] (+inf for failed trajectories), status [n]. */
+afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
+                      const int32_t *target_id, const double *targets, int32_t n_targets,
+                      double *J, int32_t *status, afm_stream_t stream);
+
+/* Initialise a swarm (Sec. 3.4): z, v drawn uniformly over the search box (z ~ U[0,1),
+ * v = U[0,1) - z), pbest_z = z, pbest_J = gbest_J = +inf, gen_to_cutoff = -1, theta = SI of z.
+ * Random numbers: Philox4x32-10 with key (low 32 bits of seed, swarm) and counter
+ * (0, particle, dim << 8 | purpose, high 32 bits of seed), purpose 1 for z, 2 for v; the
+ * uniform is ((x0 >> 5) 2^26 + (x1 >> 6)) 2^-53. */
+afm_status afm_swarm_init(afm_plan *plan, afm_swarm *swarm, uint64_t seed, afm_stream_t stream);
+
+/* One PSO generation given J [S*P] of the current positions: personal bests (strict <,
+ * non-finite J never becomes a best), swarm best (lowest pbest_J, ties to the lowest index),
+ * gen_to_cutoff, and -- unless is_last -- the Eq. 8 move v = w v + c1 r1 (pbest - z)
+ * + c2 r2 (gbest - z) with r1, r2 from counter (iter, particle, dim << 8 | 0, seed_hi), v
+ * clamped to [-vmax, vmax], z = z + v, a coordinate leaving [0,1] is clamped with v = 0; theta
+ * is refreshed.  FP64, evaluated in a fixed order without contraction (bit-reproducible). */
+afm_status afm_pso_step(afm_plan *plan, afm_swarm *swarm, const double *J, uint64_t seed,
+                        int32_t iter, int32_t is_last, double cutoff, afm_stream_t stream);
+
+/* Whole inversions (IP, Sec. 2.3) of S independent targets, one swarm of P particles each, T
+ * generations: init, then T x [misfit of every particle -> PSO generation], captured once as
+ * a HIP graph and replayed without host round-trips.  targets: [S][W] (device); n_cycles: [S]
+ * per-target period counts or NULL.  Outputs (device): best_theta [n_free][S] SI, best_J [S],
+ * gen_to_cutoff [S].  Workspace is owned by the plan. */
+afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
+                      const int32_t *n_cycles, int32_t particles, int32_t iters, uint64_t seed,
+                      double cutoff, double *best_theta, double *best_J, int32_t *gen_to_cutoff,
+                      afm_stream_t stream);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *afm_last_error(void);
+
+/* Library version string. */
+const char *afm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFM_H */

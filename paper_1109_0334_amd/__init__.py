@@ -1,0 +1,281 @@
+"""MI355X tip-sample force inversion (dynamic AFM), Python binding of libafm.so.
+
+The binding only marshals arguments: torch tensors provide device memory and the current HIP
+stream, every computation runs in the library's HIP kernels.  Names follow the C ABI in
+``include/afm.h``:
+
+* :meth:`Plan.forward_batch` -- FP of Sec. 2.2: lock-in amplitude/phase (and window trace) of a
+  batch of parameter points;
+* :meth:`Plan.misfit` -- the cost J of Eq. 5 on the lock-in window against measured traces;
+* :meth:`Plan.swarm_init`, :meth:`Plan.pso_step` -- the particle swarm of Sec. 3.4 (Eq. 8);
+* :meth:`Plan.invert` -- whole inversions (IP of Sec. 2.3) replayed as one HIP graph.
+
+There is no CPU fallback: if the library is missing or cannot be loaded, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafm.so")
+
+MAX_MODES = 4
+MAX_PARAMS = 8
+PREC = {"mixed": 0, "fp64": 1}
+LAW = {"dmt": 0, "lj": 1, "kv": 2, "hooke": 3, "sd": 4, "none": 5}
+LAW_PARAMS = {
+    "dmt": ("zc", "H", "Estar", "a0", "R"),
+    "lj": ("zc", "eps", "r0", "n", "m"),
+    "kv": ("zc", "H", "Estar", "a0", "R", "eta"),
+    "hooke": ("zc", "ks"),
+    "sd": ("zc", "ks", "zeta_s"),
+    "none": ("zc",),
+}
+IC = {"free_steady": 0, "rest": 1}
+ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
+EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
+           "afm_swarm_init", "afm_pso_step", "afm_invert", "afm_last_error", "afm_version")
+
+
+class AfmError(RuntimeError):
+    pass
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_modes", C.c_int32), ("law", C.c_int32), ("steps_per_cycle", C.c_int32),
+        ("n_cycles", C.c_int32), ("lockin_cycles", C.c_int32), ("ic", C.c_int32),
+        ("k", C.c_double), ("f0", C.c_double), ("drive_freq", C.c_double),
+        ("free_amplitude", C.c_double), ("div_limit", C.c_double),
+        ("q", C.c_double * MAX_MODES), ("ratio", C.c_double * MAX_MODES),
+        ("gain", C.c_double * MAX_MODES),
+        ("params", C.c_double * MAX_PARAMS), ("n_free", C.c_int32),
+        ("free_index", C.c_int32 * MAX_PARAMS), ("lo", C.c_double * MAX_PARAMS),
+        ("hi", C.c_double * MAX_PARAMS), ("log_scale", C.c_int32 * MAX_PARAMS),
+        ("pso_w", C.c_double), ("pso_c1", C.c_double), ("pso_c2", C.c_double),
+        ("pso_vmax", C.c_double),
+    ]
+
+
+class _Swarm(C.Structure):
+    _fields_ = [
+        ("n_dim", C.c_int32), ("particles", C.c_int32), ("swarms", C.c_int32),
+        ("z", C.c_void_p), ("v", C.c_void_p), ("pbest_z", C.c_void_p), ("pbest_J", C.c_void_p),
+        ("gbest_z", C.c_void_p), ("gbest_J", C.c_void_p), ("gen_to_cutoff", C.c_void_p),
+        ("theta", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libafm.so (built in-tree by ``paper_1109_0334_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise AfmError(f"{LIB_PATH} is missing: build it with python -m paper_1109_0334_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    L.afm_plan_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(vp)]
+    L.afm_plan_destroy.argtypes = [vp]
+    L.afm_forward_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.afm_misfit.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp]
+    L.afm_swarm_init.argtypes = [vp, C.POINTER(_Swarm), u64, vp]
+    L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
+    L.afm_invert.argtypes = [vp, i32, vp, vp, i32, i32, u64, dbl, vp, vp, vp, vp]
+    L.afm_last_error.restype = C.c_char_p
+    L.afm_version.restype = C.c_char_p
+    for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
+              "afm_swarm_init", "afm_pso_step", "afm_invert"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        msg = lib().afm_last_error().decode()
+        raise AfmError(f"{what} failed (status {code}): {msg}")
+
+
+def make_problem(model: dict, params, free=(), pso=None) -> _Problem:
+    """afm_problem from a model dict (SI; keys as in ``workloads``), the full law parameter vector
+    and the free-parameter spec [(index, lo, hi, log_scale), ...]."""
+    p = _Problem()
+    law = model["law"]
+    p.law = LAW[law] if isinstance(law, str) else int(law)
+    ic = model.get("ic", "free_steady")
+    p.ic = IC[ic] if isinstance(ic, str) else int(ic)
+    p.n_modes = int(model.get("n_modes", 1))
+    p.steps_per_cycle = int(model["steps_per_cycle"])
+    p.n_cycles = int(model["n_cycles"])
+    p.lockin_cycles = int(model["lockin_cycles"])
+    p.k, p.f0 = float(model["k"]), float(model["f0"])
+    p.drive_freq = float(model.get("drive_freq", model["f0"]))
+    p.free_amplitude = float(model["free_amplitude"])
+    p.div_limit = float(model.get("div_limit", 100.0))
+    nm = p.n_modes
+    for i, (q, r, g) in enumerate(zip(model.get("q", [400.0] * nm), model.get("ratio", [1.0] * nm),
+                                      model.get("gain", [1.0] * nm))):
+        if i < nm:
+            p.q[i], p.ratio[i], p.gain[i] = float(q), float(r), float(g)
+    for j, v in enumerate(np.asarray(params, dtype=np.float64)):
+        p.params[j] = float(v)
+    p.n_free = len(free)
+    for j, (idx, lo, hi, lg) in enumerate(free):
+        p.free_index[j], p.lo[j], p.hi[j], p.log_scale[j] = int(idx), float(lo), float(hi), int(bool(lg))
+    pso = pso or {}
+    p.pso_w, p.pso_c1 = float(pso.get("w", 0.0)), float(pso.get("c1", 0.0))
+    p.pso_c2, p.pso_vmax = float(pso.get("c2", 0.0)), float(pso.get("vmax", 0.0))
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(x, device):
+    import torch
+
+    return torch.as_tensor(np.asarray(x) if not isinstance(x, torch.Tensor) else x,
+                           dtype=torch.float64, device=device).contiguous()
+
+
+def _dev_i32(x, device):
+    import torch
+
+    if x is None:
+        return None
+    return torch.as_tensor(np.asarray(x) if not isinstance(x, torch.Tensor) else x,
+                           dtype=torch.int32, device=device).contiguous()
+
+
+class Swarm:
+    """Swarm state as device tensors in the library's structure-of-arrays layout."""
+
+    def __init__(self, D, P, S, device):
+        import torch
+
+        n = S * P
+        f = dict(dtype=torch.float64, device=device)
+        self.D, self.P, self.S = D, P, S
+        self.z, self.v, self.pbest_z = (torch.empty(D, n, **f) for _ in range(3))
+        self.theta = torch.empty(D, n, **f)
+        self.pbest_J = torch.empty(n, **f)
+        self.gbest_z = torch.empty(D, S, **f)
+        self.gbest_J = torch.empty(S, **f)
+        self.gen_to_cutoff = torch.empty(S, dtype=torch.int32, device=device)
+
+    def cstruct(self) -> _Swarm:
+        s = _Swarm()
+        s.n_dim, s.particles, s.swarms = self.D, self.P, self.S
+        for f in ("z", "v", "pbest_z", "pbest_J", "gbest_z", "gbest_J", "gen_to_cutoff", "theta"):
+            setattr(s, f, getattr(self, f).data_ptr())
+        return s
+
+
+class Plan:
+    """An afm_plan: problem constants and tables resident on the current GPU."""
+
+    def __init__(self, model: dict, params, free=(), precision="mixed", pso=None, device="cuda"):
+        import torch
+
+        self.device = torch.device(device)
+        self.model = dict(model)
+        self.free = list(free)
+        self.n_free = len(self.free)
+        self.W = int(model["lockin_cycles"]) * int(model["steps_per_cycle"])
+        self._prob = make_problem(model, params, self.free, pso)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().afm_plan_create(C.byref(self._prob), PREC[precision], C.byref(h)),
+                   "afm_plan_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().afm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward_batch(self, theta, n_cycles=None, trace=False):
+        """theta [n_free][n] (SI) -> dict(amp [n] m, phase [n] rad, status [n], trace [n][W])."""
+        import torch
+
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, -1) if self.n_free else \
+            torch.empty(0, 1, dtype=torch.float64, device=self.device)
+        n = theta.shape[1]
+        amp = torch.empty(n, dtype=torch.float64, device=self.device)
+        phase = torch.empty_like(amp)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        tr = torch.empty(n, self.W, dtype=torch.float64, device=self.device) if trace else None
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_forward_batch(self._h, n, _ptr(theta), _ptr(nc), _ptr(amp), _ptr(phase),
+                                       _ptr(tr), _ptr(status), _stream()), "afm_forward_batch")
+        return {"amp": amp, "phase": phase, "status": status, "trace": tr}
+
+    def misfit(self, theta, targets, target_id=None, n_cycles=None):
+        """theta [n_free][n], targets [n_targets][W] (m) -> (J [n], status [n])."""
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, -1)
+        n = theta.shape[1]
+        targets = _dev_f64(targets, self.device).reshape(-1, self.W)
+        import torch
+
+        J = torch.empty(n, dtype=torch.float64, device=self.device)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        tid = _dev_i32(target_id, self.device)
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_misfit(self._h, n, _ptr(theta), _ptr(nc), _ptr(tid), _ptr(targets),
+                                targets.shape[0], _ptr(J), _ptr(status), _stream()), "afm_misfit")
+        return J, status
+
+    def swarm_init(self, particles, swarms=1, seed=0) -> Swarm:
+        sw = Swarm(self.n_free, particles, swarms, self.device)
+        sw._c = sw.cstruct()
+        _check(lib().afm_swarm_init(self._h, C.byref(sw._c), int(seed) & (2**64 - 1), _stream()),
+               "afm_swarm_init")
+        return sw
+
+    def pso_step(self, sw: Swarm, J, seed, it, is_last, cutoff=0.0):
+        J = _dev_f64(J, self.device)
+        _check(lib().afm_pso_step(self._h, C.byref(sw._c), _ptr(J), int(seed) & (2**64 - 1),
+                                  int(it), int(bool(is_last)), float(cutoff), _stream()),
+               "afm_pso_step")
+
+    def invert(self, targets, particles, iters, seed=0, cutoff=0.0, n_cycles=None, out=None):
+        """S inversions (one swarm per target row) -> dict(best_theta [D][S], best_J, gen)."""
+        import torch
+
+        targets = _dev_f64(targets, self.device).reshape(-1, self.W)
+        S = targets.shape[0]
+        if out is None:
+            out = {"best_theta": torch.empty(self.n_free, S, dtype=torch.float64, device=self.device),
+                   "best_J": torch.empty(S, dtype=torch.float64, device=self.device),
+                   "gen_to_cutoff": torch.empty(S, dtype=torch.int32, device=self.device)}
+        nc = _dev_i32(n_cycles, self.device)
+        self._keep = (targets, nc)  # the captured graph refers to these buffers
+        _check(lib().afm_invert(self._h, S, _ptr(targets), _ptr(nc), int(particles), int(iters),
+                                int(seed) & (2**64 - 1), float(cutoff), _ptr(out["best_theta"]),
+                                _ptr(out["best_J"]), _ptr(out["gen_to_cutoff"]), _stream()),
+               "afm_invert")
+        return out
+
+
+def version() -> str:
+    return lib().afm_version().decode()

@@ -1,0 +1,251 @@
+// afm_internal.hpp -- shared declarations of the libafm sources (plan, kernel constants,
+// non-dimensional force laws, launch helpers).
+//
+// Non-dimensional form used by every kernel: lengths in nm, time tau = wd t, so one drive period
+// is 2 pi and one RK4 step is h = 2 pi / N.  With x_i = q_i / 1 nm the modal equations of the
+// paper (Eq. 2 with zeta_i = 1/(2 Q_i), tip-normalised modes) become
+//   x_i'' = -Om_i^2 x_i - (Om_i / Q_i) x_i' + G F(d, d') / (k 1 nm) + gamma_i a_nm sin(tau),
+// Om_i = w_i / wd, G = (w_0 / wd)^2, d = z_c + sum x_i in nm.  The force law returns the whole
+// G F / (k 1 nm) term, so each law folds G, k and the unit conversions into per-trajectory
+// constants once (in FP64) before the time loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <type_traits>
+
+#include "afm.h"
+
+namespace afm {
+
+constexpr int kMaxModes = AFM_MAX_MODES;
+constexpr int kMaxParams = AFM_MAX_PARAMS;
+constexpr int kMaxSteps = 4096;  // steps per drive period
+
+// Constants shared by every forward launch of a plan; passed by value as a kernel argument so
+// that they sit in scalar registers.
+struct KConst {
+    int32_t nm;            // modes
+    int32_t law;           // AFM_LAW_*
+    int32_t N;             // steps per period
+    int32_t n_cycles;      // default periods per trajectory
+    int32_t lockin;        // lock-in periods
+    int32_t n_free;        // free parameters
+    int32_t free_index[kMaxParams];
+    double params[kMaxParams];  // full SI parameter vector (free slots overwritten per lane)
+    double k;              // first-mode stiffness, N/m
+    double wd;             // drive angular frequency, rad/s
+    double G;              // (w0 / wd)^2
+    double h;              // 2 pi / N
+    double div_nm;         // divergence threshold on |u|, nm
+    double om2[kMaxModes];    // (w_i / wd)^2
+    double cdamp[kMaxModes];  // w_i / (wd Q_i)
+    double gain[kMaxModes];   // gamma_i
+    double y0[2 * kMaxModes]; // initial (x_i, x_i') in nm
+    const float *drive_f;     // [2N + 1] g a_nm sin(pi j / N), FP32 (g = gamma_1 for a point
+                              // mass, else 1)
+    const double *drive_d;    // [2N + 1] same, FP64
+    const double *lock_c;     // [N + 1] cos(2 pi p / N), entry N = entry 0
+    const double *lock_s;     // [N + 1] sin(2 pi p / N)
+};
+
+// ------------------------------------------------------------------------------------------
+// precision-specific primitives: FP32 uses the hardware approximations (v_rcp_f32,
+// v_sqrt_f32, v_log_f32, v_exp_f32, about 1 ulp); FP64 uses the correctly rounded operations.
+
+template <typename R> struct Ops;
+template <> struct Ops<float> {
+    __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ static inline float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+    __device__ static inline float log2(float x) { return __builtin_amdgcn_logf(x); }
+    __device__ static inline float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+    __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+};
+template <> struct Ops<double> {
+    __device__ static inline double rcp(double x) { return 1.0 / x; }
+    __device__ static inline double sqrt(double x) { return ::sqrt(x); }
+    __device__ static inline double log2(double x) { return ::log2(x); }
+    __device__ static inline double exp2(double x) { return ::exp2(x); }
+    __device__ static inline double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+};
+
+// 10^-4.5: sqrt(1 nm) in sqrt(m), used by the Hertz and Kelvin-Voigt terms.
+constexpr double kSqrtNano = 3.1622776601683794e-05;
+
+// ------------------------------------------------------------------------------------------
+// Force laws.  Each holds its per-trajectory constants in R; add(d, dd, b) returns
+// b + G F / (k 1 nm) for gap d (nm) and gap rate dd (nm per unit tau), written so that the
+// addition folds into the law's last multiply.
+
+template <int LAW, typename R> struct Law;
+
+// DMT: out of contact BH / d^2 with BH = -G H R / (6 k) (nm^3); in contact
+// BH / a0^2 + BE (a0 - d)^{3/2} with BE = G (4/3) E* sqrt(R) 10^-4.5 / k.
+template <typename R> struct Law<AFM_LAW_DMT, R> {
+    static constexpr bool kRate = false;
+    R zc, a0, BH, BHa, BE;
+    __device__ Law(const double *p, const KConst &K) {
+        const double a0n = p[3] * 1e9;
+        const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        zc = (R)(p[0] * 1e9);
+        a0 = (R)a0n;
+        BH = (R)bh;
+        BHa = (R)(bh / (a0n * a0n));
+        BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
+    }
+    __device__ inline R add(R d, R, R b) const {
+        R f;
+        if (d > a0) {
+            const R r = Ops<R>::rcp(d);
+            f = Ops<R>::fma(BH * r, r, b);
+        } else {
+            const R del = a0 - d;
+            f = Ops<R>::fma(BE * del, Ops<R>::sqrt(del), b + BHa);
+        }
+        return f;
+    }
+};
+
+// Lennard-Jones type: BL / d [(r0/d)^n - (r0/d)^m], BL = G eps n m / (n - m) / (k 1e-18).
+// Powers as exp2(n (log2 r0 - log2 d)); d <= 0 gives NaN.
+template <typename R> struct Law<AFM_LAW_LJ, R> {
+    static constexpr bool kRate = false;
+    R zc, BL, lr0, n, m;
+    __device__ Law(const double *p, const KConst &K) {
+        zc = (R)(p[0] * 1e9);
+        BL = (R)(K.G * p[1] * p[3] * p[4] / (p[3] - p[4]) / (K.k * 1e-18));
+        lr0 = (R)::log2(p[2] * 1e9);
+        n = (R)p[3];
+        m = (R)p[4];
+    }
+    __device__ inline R add(R d, R, R b) const {
+        const R ls = lr0 - Ops<R>::log2(d);
+        return Ops<R>::fma(BL * Ops<R>::rcp(d), Ops<R>::exp2(n * ls) - Ops<R>::exp2(m * ls), b);
+    }
+};
+
+// Kelvin-Voigt contact: DMT plus BV sqrt(a0 - d) d' in contact, BV = -G eta wd sqrt(R)
+// 10^-4.5 / k (the viscous force -eta sqrt(R delta) d' with d' = wd 1 nm x').
+template <typename R> struct Law<AFM_LAW_KV, R> {
+    static constexpr bool kRate = true;
+    R zc, a0, BH, BHa, BE, BV;
+    __device__ Law(const double *p, const KConst &K) {
+        const double a0n = p[3] * 1e9;
+        const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        zc = (R)(p[0] * 1e9);
+        a0 = (R)a0n;
+        BH = (R)bh;
+        BHa = (R)(bh / (a0n * a0n));
+        BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
+        BV = (R)(-K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k);
+    }
+    __device__ inline R add(R d, R dd, R b) const {
+        R f;
+        if (d > a0) {
+            const R r = Ops<R>::rcp(d);
+            f = Ops<R>::fma(BH * r, r, b);
+        } else {
+            const R del = a0 - d;
+            const R s = Ops<R>::sqrt(del);
+            f = Ops<R>::fma(s, Ops<R>::fma(BE, del, BV * dd), b + BHa);
+        }
+        return f;
+    }
+};
+
+// Hooke (Eq. 3): BK d for d < 0, BK = -G k_s / k.
+template <typename R> struct Law<AFM_LAW_HOOKE, R> {
+    static constexpr bool kRate = false;
+    R zc, BK;
+    __device__ Law(const double *p, const KConst &K) {
+        zc = (R)(p[0] * 1e9);
+        BK = (R)(-K.G * p[1] / K.k);
+    }
+    __device__ inline R add(R d, R, R b) const { return d < R(0) ? Ops<R>::fma(BK, d, b) : b; }
+};
+
+// Spring-damper (Eq. 4): BK d + BS d' for d < 0, BS = -G zeta_s wd / k.
+template <typename R> struct Law<AFM_LAW_SD, R> {
+    static constexpr bool kRate = true;
+    R zc, BK, BS;
+    __device__ Law(const double *p, const KConst &K) {
+        zc = (R)(p[0] * 1e9);
+        BK = (R)(-K.G * p[1] / K.k);
+        BS = (R)(-K.G * p[2] * K.wd / K.k);
+    }
+    __device__ inline R add(R d, R dd, R b) const {
+        return d < R(0) ? Ops<R>::fma(BK, d, Ops<R>::fma(BS, dd, b)) : b;
+    }
+};
+
+template <typename R> struct Law<AFM_LAW_NONE, R> {
+    static constexpr bool kRate = false;
+    R zc;
+    __device__ Law(const double *p, const KConst &) { zc = (R)(p[0] * 1e9); }
+    __device__ inline R add(R, R, R b) const { return b; }
+};
+
+// ------------------------------------------------------------------------------------------
+// Forward launch description (device pointers; see afm_forward_batch / afm_misfit).
+struct FwdArgs {
+    int64_t n;                 // trajectories
+    int64_t ld;                // leading dimension of theta ([n_free][ld])
+    const double *theta;
+    const int32_t *n_cycles;   // per trajectory (or per group, see group) or NULL
+    const int32_t *target_id;  // per trajectory or NULL
+    const double *targets;     // [n_targets][W] or NULL
+    int32_t n_targets;
+    int32_t group;             // > 0: n_cycles and target row are indexed by i / group
+    double *amp, *phase, *J, *trace;
+    int32_t *status;
+};
+
+// ------------------------------------------------------------------------------------------
+// host side
+
+struct GraphCache;
+
+}  // namespace afm
+
+struct afm_plan {
+    afm_problem prob;
+    int32_t precision;
+    int32_t device;
+    afm::KConst kc;
+    float *d_drive_f = nullptr;
+    double *d_drive_d = nullptr;
+    double *d_lock = nullptr;       // [2 (N + 1)]
+    hipStream_t stream = nullptr;   // private stream used to capture and replay graphs
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // plan-owned workspace for afm_invert
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    afm::GraphCache *graph = nullptr;
+    // PSO constants
+    double pso_w, pso_c1, pso_c2, pso_vmax;
+};
+
+namespace afm {
+
+// thread-local error text
+void set_error(const std::string &msg);
+afm_status fail(afm_status code, const std::string &msg);
+afm_status hip_fail(hipError_t e, const char *what);
+
+// launchers (forward.hip, pso.hip)
+hipError_t launch_forward(const afm_plan *plan, const FwdArgs &a, hipStream_t s);
+hipError_t launch_swarm_init(const afm_plan *plan, const afm_swarm &sw, uint64_t seed,
+                             hipStream_t s);
+hipError_t launch_pso_step(const afm_plan *plan, const afm_swarm &sw, const double *J,
+                           uint64_t seed, int32_t iter, int32_t is_last, double cutoff,
+                           hipStream_t s);
+hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double *best_theta,
+                              double *best_J, int32_t *gen, hipStream_t s);
+
+// argument checks shared by the entry points
+afm_status check_forward_args(const afm_plan *plan, int64_t n, const double *theta);
+
+}  // namespace afm

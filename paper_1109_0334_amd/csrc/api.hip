@@ -1,0 +1,267 @@
+// api.hip -- the extern "C" entry points of libafm: plan set-up (non-dimensionalisation, base
+// amplitude, initial state, drive and lock-in tables), argument validation, and dispatch to
+// the forward and swarm kernels.  Host code only.
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "afm_internal.hpp"
+
+namespace afm {
+
+namespace {
+thread_local std::string g_err;
+const int kLawParams[6] = {5, 5, 6, 2, 3, 1};
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+afm_status fail(afm_status code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+afm_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return AFM_ERR_HIP;
+}
+
+afm_status check_forward_args(const afm_plan *plan, int64_t n, const double *theta) {
+    if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
+    if (n < 0) return fail(AFM_ERR_INVALID, "n < 0");
+    if (n > 0 && plan->prob.n_free > 0 && !theta) return fail(AFM_ERR_INVALID, "theta is NULL");
+    if (n > (int64_t)1 << 40) return fail(AFM_ERR_INVALID, "n too large");
+    return AFM_OK;
+}
+
+// Validate a problem and fill the plan's constants.  The base amplitude follows from the free
+// linear response H_i = gamma_i / (Om_i^2 - 1 + i Om_i / Q_i) (per unit base amplitude, in units
+// of wd): a = A0 / |sum_i H_i|.  The free steady state at t = 0 is x_i = Im(a H_i),
+// x_i' = Re(a H_i) (per unit tau).
+static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_plan *plan,
+                                  std::vector<float> &drive_f, std::vector<double> &drive_d,
+                                  std::vector<double> &lock) {
+    if (precision != AFM_PREC_MIXED && precision != AFM_PREC_FP64)
+        return fail(AFM_ERR_INVALID, "precision must be AFM_PREC_MIXED or AFM_PREC_FP64");
+    if (pr.n_modes < 1 || pr.n_modes > kMaxModes) return fail(AFM_ERR_INVALID, "n_modes out of range");
+    if (pr.law < 0 || pr.law > AFM_LAW_NONE) return fail(AFM_ERR_INVALID, "unknown law");
+    if (pr.steps_per_cycle < 4 || pr.steps_per_cycle > kMaxSteps)
+        return fail(AFM_ERR_INVALID, "steps_per_cycle must be in [4, 4096]");
+    if (pr.lockin_cycles < 1) return fail(AFM_ERR_INVALID, "lockin_cycles must be >= 1");
+    if (pr.n_cycles < pr.lockin_cycles) return fail(AFM_ERR_INVALID, "n_cycles < lockin_cycles");
+    if ((int64_t)pr.lockin_cycles * pr.steps_per_cycle > (int64_t)1 << 30)
+        return fail(AFM_ERR_INVALID, "lock-in window too long");
+    if (!(pr.k > 0) || !(pr.f0 > 0) || !(pr.drive_freq > 0) || !(pr.free_amplitude > 0))
+        return fail(AFM_ERR_INVALID, "k, f0, drive_freq and free_amplitude must be positive");
+    if (pr.ic != AFM_IC_FREE_STEADY && pr.ic != AFM_IC_REST) return fail(AFM_ERR_INVALID, "unknown ic");
+    for (int i = 0; i < pr.n_modes; ++i)
+        if (!(pr.q[i] > 0) || !(pr.ratio[i] > 0) || !std::isfinite(pr.gain[i]))
+            return fail(AFM_ERR_INVALID, "mode quality factors and ratios must be positive");
+    const int np = kLawParams[pr.law];
+    if (pr.n_free < 0 || pr.n_free > np) return fail(AFM_ERR_INVALID, "n_free out of range for the law");
+    for (int j = 0; j < pr.n_free; ++j) {
+        if (pr.free_index[j] < 0 || pr.free_index[j] >= np)
+            return fail(AFM_ERR_INVALID, "free_index out of range for the law");
+        for (int l = 0; l < j; ++l)
+            if (pr.free_index[l] == pr.free_index[j]) return fail(AFM_ERR_INVALID, "free_index repeated");
+        if (!(pr.lo[j] < pr.hi[j])) return fail(AFM_ERR_INVALID, "search box needs lo < hi");
+        if (pr.log_scale[j] && !(pr.lo[j] > 0)) return fail(AFM_ERR_INVALID, "log-scaled box needs lo > 0");
+    }
+
+    KConst &K = plan->kc;
+    std::memset(&K, 0, sizeof(K));
+    K.nm = pr.n_modes;
+    K.law = pr.law;
+    K.N = pr.steps_per_cycle;
+    K.n_cycles = pr.n_cycles;
+    K.lockin = pr.lockin_cycles;
+    K.n_free = pr.n_free;
+    for (int j = 0; j < kMaxParams; ++j) {
+        K.free_index[j] = j < pr.n_free ? pr.free_index[j] : -1;
+        K.params[j] = j < np ? pr.params[j] : 0.0;
+    }
+    K.k = pr.k;
+    K.wd = 2.0 * M_PI * pr.drive_freq;
+    const double fr = pr.f0 / pr.drive_freq;
+    K.G = fr * fr;
+    K.h = 2.0 * M_PI / pr.steps_per_cycle;
+    std::complex<double> Hs(0.0, 0.0);
+    std::complex<double> H[kMaxModes];
+    for (int i = 0; i < pr.n_modes; ++i) {
+        const double Om = pr.ratio[i] * fr;
+        K.om2[i] = Om * Om;
+        K.cdamp[i] = Om / pr.q[i];
+        K.gain[i] = pr.gain[i];
+        H[i] = pr.gain[i] / std::complex<double>(Om * Om - 1.0, Om / pr.q[i]);
+        Hs += H[i];
+    }
+    if (!(std::abs(Hs) > 0)) return fail(AFM_ERR_INVALID, "free response vanishes (zero drive gains)");
+    const double a_nm = pr.free_amplitude * 1e9 / std::abs(Hs);
+    for (int i = 0; i < pr.n_modes; ++i) {
+        if (pr.ic == AFM_IC_FREE_STEADY) {
+            K.y0[i] = (a_nm * H[i]).imag();
+            K.y0[pr.n_modes + i] = (a_nm * H[i]).real();
+        }
+    }
+    K.div_nm = (pr.div_limit > 0 ? pr.div_limit : 100.0) * pr.free_amplitude * 1e9;
+    const int N = pr.steps_per_cycle;
+    drive_f.resize(2 * N + 1);
+    drive_d.resize(2 * N + 1);
+    // a point mass takes its gain into the table (the kernel then adds the entry directly)
+    const double tab_gain = pr.n_modes == 1 ? pr.gain[0] : 1.0;
+    for (int j = 0; j <= 2 * N; ++j) {
+        const double d = j == 2 * N ? 0.0 : tab_gain * a_nm * std::sin(M_PI * (double)j / (double)N);
+        drive_d[j] = d;
+        drive_f[j] = (float)d;
+    }
+    lock.resize(2 * (N + 1));
+    for (int p = 0; p <= N; ++p) {
+        const int q = p == N ? 0 : p;
+        lock[p] = std::cos(2.0 * M_PI * (double)q / (double)N);
+        lock[N + 1 + p] = std::sin(2.0 * M_PI * (double)q / (double)N);
+    }
+    plan->pso_w = pr.pso_w != 0 ? pr.pso_w : 0.7298;
+    plan->pso_c1 = pr.pso_c1 != 0 ? pr.pso_c1 : 1.49618;
+    plan->pso_c2 = pr.pso_c2 != 0 ? pr.pso_c2 : 1.49618;
+    plan->pso_vmax = pr.pso_vmax != 0 ? pr.pso_vmax : 1.0;
+    return AFM_OK;
+}
+
+void release_graph(afm_plan *plan);  // invert.hip
+
+}  // namespace afm
+
+using namespace afm;
+
+extern "C" {
+
+const char *afm_last_error(void) { return g_err.c_str(); }
+
+const char *afm_version(void) { return "afm-mi355x 0.1 (gfx950)"; }
+
+afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_plan **out) {
+    if (!out) return fail(AFM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!problem) return fail(AFM_ERR_INVALID, "problem is NULL");
+    afm_plan *plan = new (std::nothrow) afm_plan();
+    if (!plan) return fail(AFM_ERR_NOMEM, "host allocation failed");
+    plan->prob = *problem;
+    plan->precision = precision;
+    std::vector<float> df;
+    std::vector<double> dd, lk;
+    afm_status st = build_constants(*problem, precision, plan, df, dd, lk);
+    if (st != AFM_OK) {
+        delete plan;
+        return st;
+    }
+    hipError_t e = hipGetDevice(&plan->device);
+    if (e == hipSuccess) e = hipMalloc(&plan->d_drive_f, df.size() * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&plan->d_drive_d, dd.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&plan->d_lock, lk.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(plan->d_drive_f, df.data(), df.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(plan->d_drive_d, dd.data(), dd.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(plan->d_lock, lk.data(), lk.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&plan->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&plan->ev_out, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        afm_status r = hip_fail(e, "afm_plan_create");
+        afm_plan_destroy(plan);
+        return r;
+    }
+    plan->kc.drive_f = plan->d_drive_f;
+    plan->kc.drive_d = plan->d_drive_d;
+    plan->kc.lock_c = plan->d_lock;
+    plan->kc.lock_s = plan->d_lock + problem->steps_per_cycle + 1;
+    *out = plan;
+    return AFM_OK;
+}
+
+afm_status afm_plan_destroy(afm_plan *plan) {
+    if (!plan) return AFM_OK;
+    if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+    release_graph(plan);
+    if (plan->ws) (void)hipFree(plan->ws);
+    if (plan->d_drive_f) (void)hipFree(plan->d_drive_f);
+    if (plan->d_drive_d) (void)hipFree(plan->d_drive_d);
+    if (plan->d_lock) (void)hipFree(plan->d_lock);
+    if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
+    if (plan->ev_out) (void)hipEventDestroy(plan->ev_out);
+    if (plan->stream) (void)hipStreamDestroy(plan->stream);
+    delete plan;
+    return AFM_OK;
+}
+
+afm_status afm_forward_batch(afm_plan *plan, int64_t n, const double *theta,
+                             const int32_t *n_cycles, double *amp, double *phase, double *trace,
+                             int32_t *status, afm_stream_t stream) {
+    afm_status st = check_forward_args(plan, n, theta);
+    if (st != AFM_OK) return st;
+    if (n > 0 && (!amp || !phase || !status)) return fail(AFM_ERR_INVALID, "amp, phase and status are required");
+    FwdArgs a{};
+    a.n = n;
+    a.ld = n;
+    a.theta = theta;
+    a.n_cycles = n_cycles;
+    a.amp = amp;
+    a.phase = phase;
+    a.trace = trace;
+    a.status = status;
+    hipError_t e = launch_forward(plan, a, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_forward_batch launch");
+}
+
+afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
+                      const int32_t *target_id, const double *targets, int32_t n_targets,
+                      double *J, int32_t *status, afm_stream_t stream) {
+    afm_status st = check_forward_args(plan, n, theta);
+    if (st != AFM_OK) return st;
+    if (n > 0 && (!targets || !J || !status)) return fail(AFM_ERR_INVALID, "targets, J and status are required");
+    if (n > 0 && n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");
+    FwdArgs a{};
+    a.n = n;
+    a.ld = n;
+    a.theta = theta;
+    a.n_cycles = n_cycles;
+    a.target_id = target_id;
+    a.targets = targets;
+    a.n_targets = n_targets;
+    a.J = J;
+    a.status = status;
+    hipError_t e = launch_forward(plan, a, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_misfit launch");
+}
+
+static afm_status check_swarm(const afm_plan *plan, const afm_swarm *sw) {
+    if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
+    if (!sw) return fail(AFM_ERR_INVALID, "swarm is NULL");
+    if (sw->n_dim != plan->prob.n_free || sw->n_dim < 1)
+        return fail(AFM_ERR_INVALID, "swarm n_dim must equal the problem's n_free (>= 1)");
+    if (sw->particles < 1 || sw->swarms < 1) return fail(AFM_ERR_INVALID, "particles and swarms must be >= 1");
+    if ((int64_t)sw->particles * sw->swarms > (int64_t)1 << 31)
+        return fail(AFM_ERR_INVALID, "swarm too large");
+    if (!sw->z || !sw->v || !sw->pbest_z || !sw->pbest_J || !sw->gbest_z || !sw->gbest_J ||
+        !sw->gen_to_cutoff || !sw->theta)
+        return fail(AFM_ERR_INVALID, "swarm array is NULL");
+    return AFM_OK;
+}
+
+afm_status afm_swarm_init(afm_plan *plan, afm_swarm *swarm, uint64_t seed, afm_stream_t stream) {
+    afm_status st = check_swarm(plan, swarm);
+    if (st != AFM_OK) return st;
+    hipError_t e = launch_swarm_init(plan, *swarm, seed, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_swarm_init launch");
+}
+
+afm_status afm_pso_step(afm_plan *plan, afm_swarm *swarm, const double *J, uint64_t seed,
+                        int32_t iter, int32_t is_last, double cutoff, afm_stream_t stream) {
+    afm_status st = check_swarm(plan, swarm);
+    if (st != AFM_OK) return st;
+    if (!J) return fail(AFM_ERR_INVALID, "J is NULL");
+    if (iter < 0) return fail(AFM_ERR_INVALID, "iter < 0");
+    hipError_t e = launch_pso_step(plan, *swarm, J, seed, iter, is_last, cutoff, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_pso_step launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// forward.hip -- batched forward solve: RK4 time integration of the base-driven modal
+// cantilever, lock-in projection and window misfit, one trajectory per lane.
+//
+// The paper integrates the modal equations (Eq. 2) with explicit fourth-order Runge-Kutta
+// (Sec. 3.2) and evaluates the cost J_L2 (Eq. 5) for every particle of the swarm (Sec. 3.4).
+// Its GPU solver gave each mode its own thread and kept modal coefficients in shared memory;
+// here a whole trajectory lives in one lane's registers (state, Kahan compensation and the law's
+// constants), so the hot loop touches no memory except the drive and lock-in tables (uniform
+// scalar loads) and, inside the lock-in window, the measured trace.
+//
+// Precision: the mixed variant integrates in FP32 with a compensated (Kahan) state update, and
+// accumulates window samples, lock-in sums and misfit in FP64; the plain variant is FP64
+// throughout.  The drive phase comes from the integer step index (table lookup), never from an
+// accumulated FP32 time.
+#include "afm_internal.hpp"
+
+namespace afm {
+
+namespace {
+
+template <int NM, typename R, class L>
+__device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&v)[NM],
+                                      const R (&om2)[NM], const R (&cd)[NM], const R (&gn)[NM],
+                                      R D, R (&a)[NM]) {
+    R u = x[0];
+#pragma unroll
+    for (int i = 1; i < NM; ++i) u += x[i];
+    R ud = R(0);
+    if constexpr (L::kRate) {
+        ud = v[0];
+#pragma unroll
+        for (int i = 1; i < NM; ++i) ud += v[i];
+    }
+    if constexpr (NM == 1) {
+        // point mass: the drive table already carries the mode's gain
+        a[0] = Ops<R>::fma(-om2[0], x[0], Ops<R>::fma(-cd[0], v[0], law.add(law.zc + u, ud, D)));
+    } else {
+        const R F = law.add(law.zc + u, ud, R(0));
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            a[i] = Ops<R>::fma(-om2[i], x[i], Ops<R>::fma(-cd[i], v[i], Ops<R>::fma(gn[i], D, F)));
+    }
+}
+
+// One classical RK4 step, c = (0, 1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6).  D0, D1, D2 are the
+// drive terms at t, t + h/2, t + h.  COMP: Kahan-compensated update of the state.
+template <int NM, bool COMP, typename R, class L>
+__device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R (&cx)[NM],
+                                         R (&cv)[NM], const R (&om2)[NM], const R (&cd)[NM],
+                                         const R (&gn)[NM], R h, R h2, R h6, R D0, R D1, R D2) {
+    R a[NM], sx[NM], sv[NM], xs[NM], vs[NM];
+    accel<NM>(law, x, v, om2, cd, gn, D0, a);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx[i] = v[i];
+        sv[i] = a[i];
+        xs[i] = x[i] + h2 * v[i];
+        vs[i] = v[i] + h2 * a[i];
+    }
+    accel<NM>(law, xs, vs, om2, cd, gn, D1, a);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        const R kx = vs[i];
+        sx[i] += R(2) * kx;
+        sv[i] += R(2) * a[i];
+        xs[i] = x[i] + h2 * kx;
+        vs[i] = v[i] + h2 * a[i];
+    }
+    accel<NM>(law, xs, vs, om2, cd, gn, D1, a);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        const R kx = vs[i];
+        sx[i] += R(2) * kx;
+        sv[i] += R(2) * a[i];
+        xs[i] = x[i] + h * kx;
+        vs[i] = v[i] + h * a[i];
+    }
+    accel<NM>(law, xs, vs, om2, cd, gn, D2, a);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx[i] += vs[i];
+        sv[i] += a[i];
+        if constexpr (COMP) {
+            const R dx = h6 * sx[i] - cx[i];
+            const R tx = x[i] + dx;
+            cx[i] = (tx - x[i]) - dx;
+            x[i] = tx;
+            const R dv = h6 * sv[i] - cv[i];
+            const R tv = v[i] + dv;
+            cv[i] = (tv - v[i]) - dv;
+            v[i] = tv;
+        } else {
+            x[i] += h6 * sx[i];
+            v[i] += h6 * sv[i];
+        }
+    }
+}
+
+template <int NM, bool COMP, typename R>
+__device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM]) {
+    double u = 0.0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        u += (double)x[i];
+        if constexpr (COMP) u -= (double)cx[i];  // Kahan: the exact state is x - c
+    }
+    return u;
+}
+
+struct LaneOut {
+    double A, phi, J;
+    int32_t st;
+};
+
+// Integrate one trajectory of nc periods and reduce it.  Urow: measured window trace (m) or
+// nullptr; trow: window trace output (m) or nullptr.
+template <int LAW, int NM, bool MIXED>
+__device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::conditional<
+                                                 MIXED, float, double>::type> &law,
+                                             const KConst &K, int nc,
+                                             const double *__restrict__ Urow,
+                                             double *__restrict__ trow) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    constexpr bool COMP = MIXED;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    const double *__restrict__ Lc = K.lock_c;
+    const double *__restrict__ Ls = K.lock_s;
+
+    R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        x[i] = (R)K.y0[i];
+        v[i] = (R)K.y0[NM + i];
+        cx[i] = R(0);
+        cv[i] = R(0);
+        om2[i] = (R)K.om2[i];
+        cd[i] = (R)K.cdamp[i];
+        gn[i] = (R)K.gain[i];
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    const int N = K.N;
+    const int c_win = nc - K.lockin;
+    const double lim = K.div_nm;
+    double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+
+    for (int c = 0; c < nc; ++c) {
+        if (c < c_win) {
+            for (int s = 0; s < N; ++s)
+                rk4_step<NM, COMP>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                   Dt[2 * s + 1], Dt[2 * s + 2]);
+        } else {
+            const int w0 = (c - c_win) * N;
+            const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
+            double Un = Up ? Up[0] : 0.0;
+            for (int s = 0; s < N; ++s) {
+                const double Uc = Un;
+                if (Up) Un = Up[s + 1 < N ? s + 1 : s];
+                rk4_step<NM, COMP>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                   Dt[2 * s + 1], Dt[2 * s + 2]);
+                const double u = sample<NM, COMP>(x, cx);
+                Sc += u * Lc[s + 1];
+                Ss += u * Ls[s + 1];
+                if (Up) {
+                    const double U = Uc * 1e9;
+                    const double e = U - u;
+                    Jn += e * e;
+                    Jd += U * U;
+                }
+                if (trow) trow[w0 + s] = u * 1e-9;
+            }
+        }
+        // end-of-period health check: every state entry finite and |u| within the limit
+        bool fin = true;
+        R u = x[0];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[i]) && isfinite(v[i]);
+#pragma unroll
+        for (int i = 1; i < NM; ++i) u += x[i];
+        if (!fin) {
+            st = AFM_ST_NONFINITE;
+            break;
+        }
+        if (fabs((double)u) > lim) {
+            st = AFM_ST_DIVERGED;
+            break;
+        }
+    }
+    LaneOut o;
+    o.st = st;
+    if (st) {
+        o.A = NAN;
+        o.phi = NAN;
+        o.J = INFINITY;
+        if (trow)
+            for (int w = 0; w < K.lockin * N; ++w) trow[w] = NAN;
+    } else {
+        const double Wn = (double)K.lockin * N;
+        const double X = 2.0 * Sc / Wn, Y = 2.0 * Ss / Wn;
+        o.A = ::sqrt(X * X + Y * Y) * 1e-9;
+        o.phi = ::atan2(-X, Y);
+        const double J = Urow ? Jn / Jd : NAN;
+        o.J = (Urow && !isfinite(J)) ? INFINITY : J;
+    }
+    return o;
+}
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    // full parameter vector: fixed values with this lane's free parameters written in
+    double p[kMaxParams];
+#pragma unroll
+    for (int q = 0; q < kMaxParams; ++q) {
+        p[q] = K.params[q];
+#pragma unroll
+        for (int j = 0; j < kMaxParams; ++j)
+            if (j < K.n_free && K.free_index[j] == q) p[q] = A.theta[(int64_t)j * A.ld + i];
+    }
+    const Law<LAW, R> law(p, K);
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int64_t W = (int64_t)K.lockin * K.N;
+    const double *Urow = nullptr;
+    bool bad = nc < K.lockin;
+    if (A.targets) {
+        const int64_t row = A.target_id ? (int64_t)A.target_id[i] : (A.group > 0 ? grp : 0);
+        bad = bad || row < 0 || row >= A.n_targets;
+        Urow = bad ? nullptr : A.targets + row * W;
+    }
+    double *trow = A.trace ? A.trace + i * W : nullptr;
+    LaneOut o;
+    if (bad) {
+        o.A = NAN;
+        o.phi = NAN;
+        o.J = INFINITY;
+        o.st = AFM_ST_BAD_INPUT;
+        if (trow)
+            for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
+    } else {
+        o = integrate<LAW, NM, MIXED>(law, K, nc, Urow, trow);
+    }
+    if (A.amp) A.amp[i] = o.A;
+    if (A.phase) A.phase[i] = o.phi;
+    if (A.J) A.J[i] = o.J;
+    if (A.status) A.status[i] = o.st;
+}
+
+template <int LAW, int NM, bool MIXED>
+hipError_t launch_t(const FwdArgs &a, const KConst &K, hipStream_t s) {
+    // Each lane is an independent trajectory: small batches use one-wave blocks so that the
+    // waves spread over as many CUs as possible; large ones use 4-wave blocks.
+    const int block = a.n < 65536 ? 64 : 256;
+    const int64_t grid = (a.n + block - 1) / block;
+    hipLaunchKernelGGL((k_forward<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0, s, a,
+                       K);
+    return hipGetLastError();
+}
+
+template <int LAW, bool MIXED>
+hipError_t launch_modes(const FwdArgs &a, const KConst &K, hipStream_t s) {
+    switch (K.nm) {
+    case 1: return launch_t<LAW, 1, MIXED>(a, K, s);
+    case 2: return launch_t<LAW, 2, MIXED>(a, K, s);
+    case 3: return launch_t<LAW, 3, MIXED>(a, K, s);
+    case 4: return launch_t<LAW, 4, MIXED>(a, K, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool MIXED>
+hipError_t launch_law(const FwdArgs &a, const KConst &K, hipStream_t s) {
+    switch (K.law) {
+    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(a, K, s);
+    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(a, K, s);
+    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(a, K, s);
+    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(a, K, s);
+    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(a, K, s);
+    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(a, K, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_forward(const afm_plan *plan, const FwdArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (plan->precision == AFM_PREC_MIXED) return launch_law<true>(a, plan->kc, s);
+    return launch_law<false>(a, plan->kc, s);
+}
+
+}  // namespace afm

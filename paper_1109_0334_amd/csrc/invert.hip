@@ -1,0 +1,177 @@
+// invert.hip -- whole PSO inversions as one HIP graph (IP, paper Sec. 2.3 and 3.4).
+//
+// The paper keeps host-device traffic to a minimum (Sec. 3.1): here a complete inversion --
+// swarm initialisation, then for every generation the misfit of all particles followed by the
+// swarm update, then the gather of the best positions -- is captured once on the plan's private
+// stream and replayed with a single graph launch.  Generation numbers are baked into the
+// captured kernel arguments, so a replay needs no host round-trip at all.
+#include "afm_internal.hpp"
+
+namespace afm {
+
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t S = 0, P = 0, T = 0;
+    uint64_t seed = 0;
+    double cutoff = 0;
+    const double *targets = nullptr;
+    const int32_t *ncyc = nullptr;
+    double *best_theta = nullptr, *best_J = nullptr;
+    int32_t *gen = nullptr;
+    void *ws = nullptr;
+};
+
+void release_graph(afm_plan *plan) {
+    if (!plan->graph) return;
+    if (plan->graph->exec) (void)hipGraphExecDestroy(plan->graph->exec);
+    if (plan->graph->graph) (void)hipGraphDestroy(plan->graph->graph);
+    delete plan->graph;
+    plan->graph = nullptr;
+}
+
+namespace {
+
+struct WsLayout {
+    size_t bytes;
+    size_t z, v, pbest_z, theta, pbest_J, J, gbest_z, gbest_J, gen, status;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WsLayout layout(int32_t D, int32_t S, int32_t P) {
+    const size_t n = (size_t)S * P;
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.z = take(sizeof(double) * D * n);
+    L.v = take(sizeof(double) * D * n);
+    L.pbest_z = take(sizeof(double) * D * n);
+    L.theta = take(sizeof(double) * D * n);
+    L.pbest_J = take(sizeof(double) * n);
+    L.J = take(sizeof(double) * n);
+    L.gbest_z = take(sizeof(double) * D * S);
+    L.gbest_J = take(sizeof(double) * S);
+    L.gen = take(sizeof(int32_t) * S);
+    L.status = take(sizeof(int32_t) * n);
+    L.bytes = off;
+    return L;
+}
+
+afm_status ensure_workspace(afm_plan *plan, size_t bytes) {
+    if (plan->ws_bytes >= bytes) return AFM_OK;
+    hipError_t e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "afm_invert workspace sync");
+    release_graph(plan);  // captured graphs point into the old workspace
+    if (plan->ws) (void)hipFree(plan->ws);
+    plan->ws = nullptr;
+    plan->ws_bytes = 0;
+    e = hipMalloc(&plan->ws, bytes);
+    if (e != hipSuccess) return fail(AFM_ERR_NOMEM, "afm_invert: workspace allocation failed");
+    plan->ws_bytes = bytes;
+    return AFM_OK;
+}
+
+}  // namespace
+
+}  // namespace afm
+
+using namespace afm;
+
+extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
+                                 const int32_t *n_cycles, int32_t particles, int32_t iters,
+                                 uint64_t seed, double cutoff, double *best_theta,
+                                 double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream) {
+    if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
+    const int32_t D = plan->prob.n_free;
+    if (D < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
+    if (n_swarms < 1 || particles < 1 || iters < 1)
+        return fail(AFM_ERR_INVALID, "n_swarms, particles and iters must be >= 1");
+    if ((int64_t)n_swarms * particles > (int64_t)1 << 31) return fail(AFM_ERR_INVALID, "swarm too large");
+    if (!targets || !best_theta || !best_J || !gen_to_cutoff)
+        return fail(AFM_ERR_INVALID, "targets and outputs are required");
+    const WsLayout L = layout(D, n_swarms, particles);
+    afm_status st = ensure_workspace(plan, L.bytes);
+    if (st != AFM_OK) return st;
+    char *ws = (char *)plan->ws;
+    afm_swarm sw{};
+    sw.n_dim = D;
+    sw.particles = particles;
+    sw.swarms = n_swarms;
+    sw.z = (double *)(ws + L.z);
+    sw.v = (double *)(ws + L.v);
+    sw.pbest_z = (double *)(ws + L.pbest_z);
+    sw.theta = (double *)(ws + L.theta);
+    sw.pbest_J = (double *)(ws + L.pbest_J);
+    sw.gbest_z = (double *)(ws + L.gbest_z);
+    sw.gbest_J = (double *)(ws + L.gbest_J);
+    sw.gen_to_cutoff = (int32_t *)(ws + L.gen);
+    double *J = (double *)(ws + L.J);
+    int32_t *status = (int32_t *)(ws + L.status);
+
+    GraphCache *g = plan->graph;
+    const bool hit = g && g->S == n_swarms && g->P == particles && g->T == iters && g->seed == seed &&
+                     g->cutoff == cutoff && g->targets == targets && g->ncyc == n_cycles &&
+                     g->best_theta == best_theta && g->best_J == best_J && g->gen == gen_to_cutoff &&
+                     g->ws == plan->ws;
+    hipError_t e;
+    if (!hit) {
+        release_graph(plan);
+        g = new GraphCache();
+        plan->graph = g;
+        e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "afm_invert capture begin");
+        e = launch_swarm_init(plan, sw, seed, plan->stream);
+        FwdArgs a{};
+        a.n = (int64_t)n_swarms * particles;
+        a.ld = a.n;
+        a.theta = sw.theta;
+        a.n_cycles = n_cycles;
+        a.targets = targets;
+        a.n_targets = n_swarms;
+        a.group = particles;
+        a.J = J;
+        a.status = status;
+        for (int32_t t = 0; t < iters && e == hipSuccess; ++t) {
+            e = launch_forward(plan, a, plan->stream);
+            if (e == hipSuccess)
+                e = launch_pso_step(plan, sw, J, seed, t, t == iters - 1, cutoff, plan->stream);
+        }
+        if (e == hipSuccess) e = launch_gather_best(plan, sw, best_theta, best_J, gen_to_cutoff, plan->stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(plan->stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            release_graph(plan);
+            return hip_fail(e != hipSuccess ? e : e2, "afm_invert capture");
+        }
+        g->graph = graph;
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            release_graph(plan);
+            return hip_fail(e, "afm_invert graph instantiate");
+        }
+        g->S = n_swarms;
+        g->P = particles;
+        g->T = iters;
+        g->seed = seed;
+        g->cutoff = cutoff;
+        g->targets = targets;
+        g->ncyc = n_cycles;
+        g->best_theta = best_theta;
+        g->best_J = best_J;
+        g->gen = gen_to_cutoff;
+        g->ws = plan->ws;
+    }
+    // order the replay after the caller's earlier work and the caller's later work after it
+    e = hipEventRecord(plan->ev_in, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(g->exec, plan->stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_out, plan->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, plan->ev_out, 0);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_invert launch");
+}
