@@ -48,7 +48,7 @@ def parse():
 
 
 def cpu_baseline(cfg, seconds):
-    """Oracle misfit of C2 particles, one host core, until `seconds` of work (max 200)."""
+    """Oracle misfit of C2 particles, one host core, until `seconds` of work (max 4000)."""
     import numpy as np
 
     import oracle
@@ -56,12 +56,12 @@ def cpu_baseline(cfg, seconds):
     m = cfg["model"]
     base = __import__("workloads").full_params(cfg)
     U = np.sin(np.arange(m["lockin_cycles"] * m["steps_per_cycle"]) * 0.1) * 1.6e-8
-    th = __import__("workloads").draw_free(cfg, 200, 99)
+    th = __import__("workloads").draw_free(cfg, 4000, 99)
     free = __import__("workloads").free_index(cfg)
     steps_per = m["n_cycles"] * m["steps_per_cycle"]
     t0 = time.perf_counter()
     n = 0
-    while n < 200:
+    while n < 4000:
         p = base.copy()
         for j, f in enumerate(free):
             p[f[0]] = th[n, j]

@@ -63,6 +63,7 @@ template <> struct Ops<float> {
     __device__ static inline float log2(float x) { return __builtin_amdgcn_logf(x); }
     __device__ static inline float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
     __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    __device__ static inline float max(float a, float b) { return __builtin_fmaxf(a, b); }
 };
 template <> struct Ops<double> {
     __device__ static inline double rcp(double x) { return 1.0 / x; }
@@ -70,22 +71,28 @@ template <> struct Ops<double> {
     __device__ static inline double log2(double x) { return ::log2(x); }
     __device__ static inline double exp2(double x) { return ::exp2(x); }
     __device__ static inline double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    __device__ static inline double max(double a, double b) { return __builtin_fmax(a, b); }
 };
 
 // 10^-4.5: sqrt(1 nm) in sqrt(m), used by the Hertz and Kelvin-Voigt terms.
 constexpr double kSqrtNano = 3.1622776601683794e-05;
 
 // ------------------------------------------------------------------------------------------
-// Force laws.  Each holds its per-trajectory constants in R; add(d, dd, b) returns
+// Force laws.  Each holds its per-trajectory constants in R; add<BF>(d, dd, b) returns
 // b + G F / (k 1 nm) for gap d (nm) and gap rate dd (nm per unit tau), written so that the
-// addition folds into the law's last multiply.
+// addition folds into the law's last multiply.  BF selects the branch-free form of laws with a
+// contact branch (both pieces evaluated with clamped arguments, no divergent control flow: fewest
+// issue slots when one wave owns a SIMD) or the branching form (each lane evaluates only its own
+// piece: fewer transcendental ops when many waves share a SIMD).
 
 template <int LAW, typename R> struct Law;
 
-// DMT: out of contact BH / d^2 with BH = -G H R / (6 k) (nm^3); in contact
-// BH / a0^2 + BE (a0 - d)^{3/2} with BE = G (4/3) E* sqrt(R) 10^-4.5 / k.
+// DMT: out of contact BH / d^2 with BH = -G H R / (6 k) (nm^3); in contact the attraction is
+// frozen at its d = a0 value and BE (a0 - d)^{3/2} is added, BE = G (4/3) E* sqrt(R) 10^-4.5 / k.
+// Branch-free: BH / max(d, a0)^2 + BE max(a0 - d, 0)^{3/2} is the same function.
 template <typename R> struct Law<AFM_LAW_DMT, R> {
     static constexpr bool kRate = false;
+    static constexpr bool kBranch = true;
     R zc, a0, BH, BHa, BE;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
@@ -96,16 +103,22 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
         BHa = (R)(bh / (a0n * a0n));
         BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
     }
-    __device__ inline R add(R d, R, R b) const {
-        R f;
-        if (d > a0) {
-            const R r = Ops<R>::rcp(d);
-            f = Ops<R>::fma(BH * r, r, b);
+    template <bool BF> __device__ inline R add(R d, R, R b) const {
+        if constexpr (BF) {
+            const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+            const R del = Ops<R>::max(a0 - d, R(0));
+            return Ops<R>::fma(BE * del, Ops<R>::sqrt(del), Ops<R>::fma(BH * r, r, b));
         } else {
-            const R del = a0 - d;
-            f = Ops<R>::fma(BE * del, Ops<R>::sqrt(del), b + BHa);
+            R f;
+            if (d > a0) {
+                const R r = Ops<R>::rcp(d);
+                f = Ops<R>::fma(BH * r, r, b);
+            } else {
+                const R del = a0 - d;
+                f = Ops<R>::fma(BE * del, Ops<R>::sqrt(del), b + BHa);
+            }
+            return f;
         }
-        return f;
     }
 };
 
@@ -113,6 +126,7 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
 // Powers as exp2(n (log2 r0 - log2 d)); d <= 0 gives NaN.
 template <typename R> struct Law<AFM_LAW_LJ, R> {
     static constexpr bool kRate = false;
+    static constexpr bool kBranch = false;
     R zc, BL, lr0, n, m;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
@@ -121,7 +135,7 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
         n = (R)p[3];
         m = (R)p[4];
     }
-    __device__ inline R add(R d, R, R b) const {
+    template <bool BF> __device__ inline R add(R d, R, R b) const {
         const R ls = lr0 - Ops<R>::log2(d);
         return Ops<R>::fma(BL * Ops<R>::rcp(d), Ops<R>::exp2(n * ls) - Ops<R>::exp2(m * ls), b);
     }
@@ -131,6 +145,7 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
 // 10^-4.5 / k (the viscous force -eta sqrt(R delta) d' with d' = wd 1 nm x').
 template <typename R> struct Law<AFM_LAW_KV, R> {
     static constexpr bool kRate = true;
+    static constexpr bool kBranch = true;
     R zc, a0, BH, BHa, BE, BV;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
@@ -142,50 +157,62 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
         BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
         BV = (R)(-K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k);
     }
-    __device__ inline R add(R d, R dd, R b) const {
-        R f;
-        if (d > a0) {
-            const R r = Ops<R>::rcp(d);
-            f = Ops<R>::fma(BH * r, r, b);
+    template <bool BF> __device__ inline R add(R d, R dd, R b) const {
+        if constexpr (BF) {
+            const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+            const R del = Ops<R>::max(a0 - d, R(0));
+            return Ops<R>::fma(Ops<R>::sqrt(del), Ops<R>::fma(BE, del, BV * dd),
+                               Ops<R>::fma(BH * r, r, b));
         } else {
-            const R del = a0 - d;
-            const R s = Ops<R>::sqrt(del);
-            f = Ops<R>::fma(s, Ops<R>::fma(BE, del, BV * dd), b + BHa);
+            R f;
+            if (d > a0) {
+                const R r = Ops<R>::rcp(d);
+                f = Ops<R>::fma(BH * r, r, b);
+            } else {
+                const R del = a0 - d;
+                const R s = Ops<R>::sqrt(del);
+                f = Ops<R>::fma(s, Ops<R>::fma(BE, del, BV * dd), b + BHa);
+            }
+            return f;
         }
-        return f;
     }
 };
 
 // Hooke (Eq. 3): BK d for d < 0, BK = -G k_s / k.
 template <typename R> struct Law<AFM_LAW_HOOKE, R> {
     static constexpr bool kRate = false;
+    static constexpr bool kBranch = false;
     R zc, BK;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
         BK = (R)(-K.G * p[1] / K.k);
     }
-    __device__ inline R add(R d, R, R b) const { return d < R(0) ? Ops<R>::fma(BK, d, b) : b; }
+    template <bool BF> __device__ inline R add(R d, R, R b) const {
+        return d < R(0) ? Ops<R>::fma(BK, d, b) : b;
+    }
 };
 
 // Spring-damper (Eq. 4): BK d + BS d' for d < 0, BS = -G zeta_s wd / k.
 template <typename R> struct Law<AFM_LAW_SD, R> {
     static constexpr bool kRate = true;
+    static constexpr bool kBranch = false;
     R zc, BK, BS;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
         BK = (R)(-K.G * p[1] / K.k);
         BS = (R)(-K.G * p[2] * K.wd / K.k);
     }
-    __device__ inline R add(R d, R dd, R b) const {
+    template <bool BF> __device__ inline R add(R d, R dd, R b) const {
         return d < R(0) ? Ops<R>::fma(BK, d, Ops<R>::fma(BS, dd, b)) : b;
     }
 };
 
 template <typename R> struct Law<AFM_LAW_NONE, R> {
     static constexpr bool kRate = false;
+    static constexpr bool kBranch = false;
     R zc;
     __device__ Law(const double *p, const KConst &) { zc = (R)(p[0] * 1e9); }
-    __device__ inline R add(R, R, R b) const { return b; }
+    template <bool BF> __device__ inline R add(R, R, R b) const { return b; }
 };
 
 // ------------------------------------------------------------------------------------------

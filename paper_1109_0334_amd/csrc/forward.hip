@@ -18,91 +18,101 @@ namespace afm {
 
 namespace {
 
-template <int NM, typename R, class L>
+// Mode 1 is carried as the tip-sample gap g = z_c + x_1 rather than as x_1: the force laws are
+// steepest exactly where the gap is small, and there an FP32 gap keeps full relative precision
+// (forming z_c + x_1 from two ~A0-sized numbers would lose it).  The restoring force of mode 1
+// uses x_1 = g - z_c, which needs only absolute precision.
+//
+// Slopes of the modal system at state (g, x_2.., v_1..): returns the accelerations a_i.
+template <int NM, bool BF, typename R, class L>
 __device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&v)[NM],
                                       const R (&om2)[NM], const R (&cd)[NM], const R (&gn)[NM],
                                       R D, R (&a)[NM]) {
-    R u = x[0];
+    R d = x[0];
 #pragma unroll
-    for (int i = 1; i < NM; ++i) u += x[i];
-    R ud = R(0);
+    for (int i = 1; i < NM; ++i) d += x[i];
+    R dd = R(0);
     if constexpr (L::kRate) {
-        ud = v[0];
+        dd = v[0];
 #pragma unroll
-        for (int i = 1; i < NM; ++i) ud += v[i];
+        for (int i = 1; i < NM; ++i) dd += v[i];
     }
     if constexpr (NM == 1) {
         // point mass: the drive table already carries the mode's gain
-        a[0] = Ops<R>::fma(-om2[0], x[0], Ops<R>::fma(-cd[0], v[0], law.add(law.zc + u, ud, D)));
+        a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc,
+                           Ops<R>::fma(-cd[0], v[0], law.template add<BF>(d, dd, D)));
     } else {
-        const R F = law.add(law.zc + u, ud, R(0));
+        const R F = law.template add<BF>(d, dd, R(0));
+        a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc, Ops<R>::fma(-cd[0], v[0], Ops<R>::fma(gn[0], D, F)));
 #pragma unroll
-        for (int i = 0; i < NM; ++i)
+        for (int i = 1; i < NM; ++i)
             a[i] = Ops<R>::fma(-om2[i], x[i], Ops<R>::fma(-cd[i], v[i], Ops<R>::fma(gn[i], D, F)));
     }
 }
 
 // One classical RK4 step, c = (0, 1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6).  D0, D1, D2 are the
 // drive terms at t, t + h/2, t + h.  COMP: Kahan-compensated update of the state.
-template <int NM, bool COMP, typename R, class L>
+template <int NM, bool COMP, bool BF, typename R, class L>
 __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R (&cx)[NM],
                                          R (&cv)[NM], const R (&om2)[NM], const R (&cd)[NM],
                                          const R (&gn)[NM], R h, R h2, R h6, R D0, R D1, R D2) {
     R a[NM], sx[NM], sv[NM], xs[NM], vs[NM];
-    accel<NM>(law, x, v, om2, cd, gn, D0, a);
+    accel<NM, BF>(law, x, v, om2, cd, gn, D0, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         sx[i] = v[i];
         sv[i] = a[i];
-        xs[i] = x[i] + h2 * v[i];
-        vs[i] = v[i] + h2 * a[i];
+        xs[i] = Ops<R>::fma(h2, v[i], x[i]);
+        vs[i] = Ops<R>::fma(h2, a[i], v[i]);
     }
-    accel<NM>(law, xs, vs, om2, cd, gn, D1, a);
+    accel<NM, BF>(law, xs, vs, om2, cd, gn, D1, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         const R kx = vs[i];
-        sx[i] += R(2) * kx;
-        sv[i] += R(2) * a[i];
-        xs[i] = x[i] + h2 * kx;
-        vs[i] = v[i] + h2 * a[i];
+        sx[i] = Ops<R>::fma(R(2), kx, sx[i]);
+        sv[i] = Ops<R>::fma(R(2), a[i], sv[i]);
+        xs[i] = Ops<R>::fma(h2, kx, x[i]);
+        vs[i] = Ops<R>::fma(h2, a[i], v[i]);
     }
-    accel<NM>(law, xs, vs, om2, cd, gn, D1, a);
+    accel<NM, BF>(law, xs, vs, om2, cd, gn, D1, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         const R kx = vs[i];
-        sx[i] += R(2) * kx;
-        sv[i] += R(2) * a[i];
-        xs[i] = x[i] + h * kx;
-        vs[i] = v[i] + h * a[i];
+        sx[i] = Ops<R>::fma(R(2), kx, sx[i]);
+        sv[i] = Ops<R>::fma(R(2), a[i], sv[i]);
+        xs[i] = Ops<R>::fma(h, kx, x[i]);
+        vs[i] = Ops<R>::fma(h, a[i], v[i]);
     }
-    accel<NM>(law, xs, vs, om2, cd, gn, D2, a);
+    accel<NM, BF>(law, xs, vs, om2, cd, gn, D2, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         sx[i] += vs[i];
         sv[i] += a[i];
         if constexpr (COMP) {
-            const R dx = h6 * sx[i] - cx[i];
+            const R dx = Ops<R>::fma(h6, sx[i], -cx[i]);
             const R tx = x[i] + dx;
             cx[i] = (tx - x[i]) - dx;
             x[i] = tx;
-            const R dv = h6 * sv[i] - cv[i];
+            const R dv = Ops<R>::fma(h6, sv[i], -cv[i]);
             const R tv = v[i] + dv;
             cv[i] = (tv - v[i]) - dv;
             v[i] = tv;
         } else {
-            x[i] += h6 * sx[i];
-            v[i] += h6 * sv[i];
+            x[i] = Ops<R>::fma(h6, sx[i], x[i]);
+            v[i] = Ops<R>::fma(h6, sv[i], v[i]);
         }
     }
 }
 
+// Tip deflection u = g - z_c + x_2 + ... in FP64, including the Kahan residuals (the compensated
+// state is x - c).
 template <int NM, bool COMP, typename R>
-__device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM]) {
-    double u = 0.0;
+__device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM], double zc) {
+    double u = -zc;
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         u += (double)x[i];
-        if constexpr (COMP) u -= (double)cx[i];  // Kahan: the exact state is x - c
+        if constexpr (COMP) u -= (double)cx[i];
     }
     return u;
 }
@@ -112,14 +122,12 @@ struct LaneOut {
     int32_t st;
 };
 
-// Integrate one trajectory of nc periods and reduce it.  Urow: measured window trace (m) or
-// nullptr; trow: window trace output (m) or nullptr.
-template <int LAW, int NM, bool MIXED>
-__device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::conditional<
-                                                 MIXED, float, double>::type> &law,
-                                             const KConst &K, int nc,
-                                             const double *__restrict__ Urow,
-                                             double *__restrict__ trow) {
+// Integrate one trajectory of nc periods and reduce it.  zc: separation in nm (FP64).
+// Urow: measured window trace (m) or nullptr; trow: window trace output (m) or nullptr.
+template <int LAW, int NM, bool MIXED, bool BF>
+__device__ __forceinline__ LaneOut integrate(
+    const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
+    const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     const R *__restrict__ Dt;
@@ -131,7 +139,7 @@ __device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::condit
     R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
-        x[i] = (R)K.y0[i];
+        x[i] = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
         v[i] = (R)K.y0[NM + i];
         cx[i] = R(0);
         cv[i] = R(0);
@@ -148,9 +156,10 @@ __device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::condit
 
     for (int c = 0; c < nc; ++c) {
         if (c < c_win) {
+#pragma unroll 4
             for (int s = 0; s < N; ++s)
-                rk4_step<NM, COMP>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                   Dt[2 * s + 1], Dt[2 * s + 2]);
+                rk4_step<NM, COMP, BF>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                       Dt[2 * s + 1], Dt[2 * s + 2]);
         } else {
             const int w0 = (c - c_win) * N;
             const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
@@ -158,9 +167,9 @@ __device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::condit
             for (int s = 0; s < N; ++s) {
                 const double Uc = Un;
                 if (Up) Un = Up[s + 1 < N ? s + 1 : s];
-                rk4_step<NM, COMP>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                   Dt[2 * s + 1], Dt[2 * s + 2]);
-                const double u = sample<NM, COMP>(x, cx);
+                rk4_step<NM, COMP, BF>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                       Dt[2 * s + 1], Dt[2 * s + 2]);
+                const double u = sample<NM, COMP>(x, cx, zc);
                 Sc += u * Lc[s + 1];
                 Ss += u * Ls[s + 1];
                 if (Up) {
@@ -174,16 +183,13 @@ __device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::condit
         }
         // end-of-period health check: every state entry finite and |u| within the limit
         bool fin = true;
-        R u = x[0];
 #pragma unroll
         for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[i]) && isfinite(v[i]);
-#pragma unroll
-        for (int i = 1; i < NM; ++i) u += x[i];
         if (!fin) {
             st = AFM_ST_NONFINITE;
             break;
         }
-        if (fabs((double)u) > lim) {
+        if (fabs(sample<NM, COMP>(x, cx, zc)) > lim) {
             st = AFM_ST_DIVERGED;
             break;
         }
@@ -207,7 +213,7 @@ __device__ __forceinline__ LaneOut integrate(const Law<LAW, typename std::condit
     return o;
 }
 
-template <int LAW, int NM, bool MIXED>
+template <int LAW, int NM, bool MIXED, bool BF>
 __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
     using R = typename std::conditional<MIXED, float, double>::type;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -242,7 +248,7 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
         if (trow)
             for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
     } else {
-        o = integrate<LAW, NM, MIXED>(law, K, nc, Urow, trow);
+        o = integrate<LAW, NM, MIXED, BF>(law, p[0] * 1e9, K, nc, Urow, trow);
     }
     if (A.amp) A.amp[i] = o.A;
     if (A.phase) A.phase[i] = o.phi;
@@ -250,14 +256,24 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
     if (A.status) A.status[i] = o.st;
 }
 
+// Small batches (fewer waves than SIMDs) are issue-latency bound: one-wave blocks spread over
+// the CUs and the branch-free law minimises issue slots.  Large batches are throughput bound:
+// 4-wave blocks and the branching law (fewer transcendental ops).
+constexpr int64_t kSmallBatch = 65536;
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const FwdArgs &a, const KConst &K, hipStream_t s) {
-    // Each lane is an independent trajectory: small batches use one-wave blocks so that the
-    // waves spread over as many CUs as possible; large ones use 4-wave blocks.
-    const int block = a.n < 65536 ? 64 : 256;
+    const int block = a.n < kSmallBatch ? 64 : 256;
     const int64_t grid = (a.n + block - 1) / block;
-    hipLaunchKernelGGL((k_forward<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0, s, a,
-                       K);
+    if constexpr (Law<LAW, float>::kBranch) {
+        if (a.n >= kSmallBatch) {
+            hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, false>), dim3((unsigned)grid),
+                               dim3(block), 0, s, a, K);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, true>), dim3((unsigned)grid), dim3(block), 0,
+                       s, a, K);
     return hipGetLastError();
 }
 
