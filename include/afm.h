@@ -108,7 +108,11 @@ typedef struct afm_problem {
     double hi[AFM_MAX_PARAMS];
     int32_t log_scale[AFM_MAX_PARAMS];  /* 1: theta = lo (hi/lo)^z, else lo + z (hi - lo)      */
     double pso_w, pso_c1, pso_c2, pso_vmax; /* Eq. 8 weights; 0 => 0.7298, 1.49618, 1.49618, 1 */
+    int32_t polish_precision; /* arithmetic of afm_polish and the invert polish: AFM_POLISH_*   */
 } afm_problem;
+
+/* Polish arithmetic: the plan's own precision, or FP32 (mixed) / FP64 adjoint and misfits. */
+enum { AFM_POLISH_PLAN = 0, AFM_POLISH_MIXED = 1, AFM_POLISH_FP64 = 2 };
 
 typedef struct afm_plan afm_plan; /* opaque: constants, drive/lock-in tables, workspace */
 
@@ -149,6 +153,20 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
                       const int32_t *target_id, const double *targets, int32_t n_targets,
                       double *J, int32_t *status, afm_stream_t stream);
 
+/* Misfit and its exact gradient with respect to the free parameters for n points: the
+ * discrete adjoint of the forward kernel's RK4 trajectory and window misfit (reverse-mode
+ * differentiation, stages reversed; same arithmetic precision as the plan), with the state
+ * checkpointed every ckpt_stride RK4 steps and each segment recomputed for the reverse sweep.
+ * Arguments as afm_misfit; per-trajectory n_cycles must not exceed the problem's n_cycles.
+ * Outputs (device): J [n], dJ [n_free][n] = dJ/dtheta_j in 1/(SI unit of parameter j), status.
+ * ckpt_stride: RK4 steps between checkpoints, or 0 = autotuned (the first call with a new n
+ * times the strides 16, 64 and 256 and keeps the fastest; that call synchronises the stream).
+ * Workspace (checkpoints, segment buffer) is owned by the plan and grown on demand. */
+afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
+                          const int32_t *target_id, const double *targets, int32_t n_targets,
+                          double *J, double *dJ, int32_t ckpt_stride, int32_t *status,
+                          afm_stream_t stream);
+
 /* Initialise a swarm (Sec. 3.4): z, v drawn uniformly over the search box (z ~ U[0,1),
  * v = U[0,1) - z), pbest_z = z, pbest_J = gbest_J = +inf, gen_to_cutoff = -1, theta = SI of z.
  * Random numbers: Philox4x32-10 with key (low 32 bits of seed, swarm) and counter
@@ -165,15 +183,29 @@ afm_status afm_swarm_init(afm_plan *plan, afm_swarm *swarm, uint64_t seed, afm_s
 afm_status afm_pso_step(afm_plan *plan, afm_swarm *swarm, const double *J, uint64_t seed,
                         int32_t iter, int32_t is_last, double cutoff, afm_stream_t stream);
 
+/* Polish n parameter points with projected L-BFGS on the discrete-adjoint gradient, in the
+ * normalised coordinates of the problem's search box: history 5, H0 = s'y / y'y, trial steps
+ * 2^-k (k = 0..20) of the direction evaluated together, the first satisfying Armijo (c = 1e-4)
+ * accepted, a pair dropped when s'y <= 1e-12 |s||y|; a point with no acceptable step stops.
+ * z: [n_free][n] normalised positions (device, in/out); n_cycles, target_id, targets,
+ * n_targets as in afm_misfit; J: [n] misfit at the returned positions (device).  Workspace is
+ * owned by the plan.  Enqueues a fixed sequence of launches (no host synchronisation). */
+afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cycles,
+                      const int32_t *target_id, const double *targets, int32_t n_targets,
+                      int32_t steps, double *J, afm_stream_t stream);
+
 /* Whole inversions (IP, Sec. 2.3) of S independent targets, one swarm of P particles each, T
- * generations: init, then T x [misfit of every particle -> PSO generation], captured once as
+ * generations: init, then T x [misfit of every particle -> PSO generation]; then, if
+ * lbfgs_steps > 0, the lbfgs_topk best personal bests of every swarm are polished by
+ * afm_polish and the best polished point replaces the swarm best when lower.  Captured once as
  * a HIP graph and replayed without host round-trips.  targets: [S][W] (device); n_cycles: [S]
- * per-target period counts or NULL.  Outputs (device): best_theta [n_free][S] SI, best_J [S],
- * gen_to_cutoff [S].  Workspace is owned by the plan. */
+ * per-target period counts or NULL (uneven counts run through the persistent work-queue
+ * kernel, longest first).  Outputs (device): best_theta [n_free][S] SI, best_J [S],
+ * gen_to_cutoff [S].  lbfgs_topk <= particles.  Workspace is owned by the plan. */
 afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
                       const int32_t *n_cycles, int32_t particles, int32_t iters, uint64_t seed,
-                      double cutoff, double *best_theta, double *best_J, int32_t *gen_to_cutoff,
-                      afm_stream_t stream);
+                      double cutoff, int32_t lbfgs_steps, int32_t lbfgs_topk, double *best_theta,
+                      double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *afm_last_error(void);

@@ -35,9 +35,11 @@ LAW_PARAMS = {
     "none": ("zc",),
 }
 IC = {"free_steady": 0, "rest": 1}
+POLISH = {"plan": 0, "mixed": 1, "fp64": 2}
 ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
-           "afm_swarm_init", "afm_pso_step", "afm_invert", "afm_last_error", "afm_version")
+           "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
+           "afm_last_error", "afm_version")
 
 
 class AfmError(RuntimeError):
@@ -56,7 +58,7 @@ class _Problem(C.Structure):
         ("free_index", C.c_int32 * MAX_PARAMS), ("lo", C.c_double * MAX_PARAMS),
         ("hi", C.c_double * MAX_PARAMS), ("log_scale", C.c_int32 * MAX_PARAMS),
         ("pso_w", C.c_double), ("pso_c1", C.c_double), ("pso_c2", C.c_double),
-        ("pso_vmax", C.c_double),
+        ("pso_vmax", C.c_double), ("polish_precision", C.c_int32),
     ]
 
 
@@ -85,13 +87,15 @@ def lib() -> C.CDLL:
     L.afm_plan_destroy.argtypes = [vp]
     L.afm_forward_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.afm_misfit.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp]
+    L.afm_grad_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
     L.afm_swarm_init.argtypes = [vp, C.POINTER(_Swarm), u64, vp]
     L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
-    L.afm_invert.argtypes = [vp, i32, vp, vp, i32, i32, u64, dbl, vp, vp, vp, vp]
+    L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, i32, i32, vp, vp]
+    L.afm_invert.argtypes = [vp, i32, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
-              "afm_swarm_init", "afm_pso_step", "afm_invert"):
+              "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -103,7 +107,7 @@ def _check(code: int, what: str):
         raise AfmError(f"{what} failed (status {code}): {msg}")
 
 
-def make_problem(model: dict, params, free=(), pso=None) -> _Problem:
+def make_problem(model: dict, params, free=(), pso=None, polish="plan") -> _Problem:
     """afm_problem from a model dict (SI; keys as in ``workloads``), the full law parameter vector
     and the free-parameter spec [(index, lo, hi, log_scale), ...]."""
     p = _Problem()
@@ -132,6 +136,7 @@ def make_problem(model: dict, params, free=(), pso=None) -> _Problem:
     pso = pso or {}
     p.pso_w, p.pso_c1 = float(pso.get("w", 0.0)), float(pso.get("c1", 0.0))
     p.pso_c2, p.pso_vmax = float(pso.get("c2", 0.0)), float(pso.get("vmax", 0.0))
+    p.polish_precision = POLISH[polish]
     return p
 
 
@@ -188,7 +193,8 @@ class Swarm:
 class Plan:
     """An afm_plan: problem constants and tables resident on the current GPU."""
 
-    def __init__(self, model: dict, params, free=(), precision="mixed", pso=None, device="cuda"):
+    def __init__(self, model: dict, params, free=(), precision="mixed", pso=None, device="cuda",
+                 polish="plan"):
         import torch
 
         self.device = torch.device(device)
@@ -196,7 +202,7 @@ class Plan:
         self.free = list(free)
         self.n_free = len(self.free)
         self.W = int(model["lockin_cycles"]) * int(model["steps_per_cycle"])
-        self._prob = make_problem(model, params, self.free, pso)
+        self._prob = make_problem(model, params, self.free, pso, polish)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().afm_plan_create(C.byref(self._prob), PREC[precision], C.byref(h)),
@@ -245,6 +251,23 @@ class Plan:
                                 targets.shape[0], _ptr(J), _ptr(status), _stream()), "afm_misfit")
         return J, status
 
+    def grad_batch(self, theta, targets, target_id=None, n_cycles=None, ckpt_stride=0):
+        """Discrete-adjoint gradient: (J [n], dJ [n_free][n] per SI unit, status [n])."""
+        import torch
+
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, -1)
+        n = theta.shape[1]
+        targets = _dev_f64(targets, self.device).reshape(-1, self.W)
+        J = torch.empty(n, dtype=torch.float64, device=self.device)
+        dJ = torch.empty(self.n_free, n, dtype=torch.float64, device=self.device)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        tid = _dev_i32(target_id, self.device)
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_grad_batch(self._h, n, _ptr(theta), _ptr(nc), _ptr(tid), _ptr(targets),
+                                    targets.shape[0], _ptr(J), _ptr(dJ), int(ckpt_stride),
+                                    _ptr(status), _stream()), "afm_grad_batch")
+        return J, dJ, status
+
     def swarm_init(self, particles, swarms=1, seed=0) -> Swarm:
         sw = Swarm(self.n_free, particles, swarms, self.device)
         sw._c = sw.cstruct()
@@ -258,7 +281,21 @@ class Plan:
                                   int(it), int(bool(is_last)), float(cutoff), _stream()),
                "afm_pso_step")
 
-    def invert(self, targets, particles, iters, seed=0, cutoff=0.0, n_cycles=None, out=None):
+    def polish(self, z, targets, target_id=None, n_cycles=None, steps=10):
+        """L-BFGS polish of normalised positions z [n_free][n] (in place) -> J [n]."""
+        import torch
+
+        targets = _dev_f64(targets, self.device).reshape(-1, self.W)
+        n = z.shape[1]
+        J = torch.empty(n, dtype=torch.float64, device=self.device)
+        tid = _dev_i32(target_id, self.device)
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_polish(self._h, n, _ptr(z), _ptr(nc), _ptr(tid), _ptr(targets),
+                                targets.shape[0], int(steps), _ptr(J), _stream()), "afm_polish")
+        return J
+
+    def invert(self, targets, particles, iters, seed=0, cutoff=0.0, n_cycles=None, out=None,
+               lbfgs_steps=0, lbfgs_topk=0):
         """S inversions (one swarm per target row) -> dict(best_theta [D][S], best_J, gen)."""
         import torch
 
@@ -271,10 +308,46 @@ class Plan:
         nc = _dev_i32(n_cycles, self.device)
         self._keep = (targets, nc)  # the captured graph refers to these buffers
         _check(lib().afm_invert(self._h, S, _ptr(targets), _ptr(nc), int(particles), int(iters),
-                                int(seed) & (2**64 - 1), float(cutoff), _ptr(out["best_theta"]),
+                                int(seed) & (2**64 - 1), float(cutoff), int(lbfgs_steps),
+                                int(lbfgs_topk), _ptr(out["best_theta"]),
                                 _ptr(out["best_J"]), _ptr(out["gen_to_cutoff"]), _stream()),
                "afm_invert")
         return out
+
+
+def _misfit_fn():
+    import torch
+
+    class MisfitFn(torch.autograd.Function):
+        """J(theta) of afm_misfit with the discrete-adjoint gradient of afm_grad_batch.
+
+        apply(theta [n_free][n], plan, targets [, target_id, n_cycles]) -> J [n]."""
+
+        @staticmethod
+        def forward(ctx, theta, plan, targets, target_id=None, n_cycles=None):
+            J, _ = plan.misfit(theta, targets, target_id, n_cycles)
+            ctx.save_for_backward(theta)
+            ctx.plan, ctx.targets, ctx.tid, ctx.nc = plan, targets, target_id, n_cycles
+            return J
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (theta,) = ctx.saved_tensors
+            _, dJ, _ = ctx.plan.grad_batch(theta.detach(), ctx.targets, ctx.tid, ctx.nc)
+            return gJ.to(dJ.dtype)[None, :] * dJ, None, None, None, None
+
+    return MisfitFn
+
+
+_MISFIT_FN = None
+
+
+def misfit_fn():
+    """The torch.autograd.Function class over afm_misfit / afm_grad_batch."""
+    global _MISFIT_FN
+    if _MISFIT_FN is None:
+        _MISFIT_FN = _misfit_fn()
+    return _MISFIT_FN
 
 
 def version() -> str:

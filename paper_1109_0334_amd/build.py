@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libafm.so")
-SOURCES = ["api.hip", "forward.hip", "pso.hip", "invert.hip"]
+SOURCES = ["api.hip", "forward.hip", "grad.hip", "lbfgs.hip", "pso.hip", "invert.hip"]
 ARCH = os.environ.get("AFM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -120,6 +120,34 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
             return f;
         }
     }
+
+    // Gradient support: F and its partials with respect to d, d' and the constants
+    // c = (BH, BE, a0); to_si() maps accumulated dJ/dc and dJ/dz_c to SI parameter derivatives.
+    static constexpr int NC = 3;
+    __device__ inline R grad(R d, R, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        const bool out = d > a0;
+        const R m = out ? d : a0;
+        const R r = Ops<R>::rcp(m);
+        const R del = out ? R(0) : a0 - d;
+        const R s = Ops<R>::sqrt(del);
+        const R r3 = BH * r * r * r;
+        Fd = out ? R(-2) * r3 : R(-1.5) * BE * s;
+        Fdd = R(0);
+        dc[0] = r * r;
+        dc[1] = del * s;
+        dc[2] = out ? R(0) : R(-2) * r3 + R(1.5) * BE * s;
+        return Ops<R>::fma(BH * r, r, BE * del * s);
+    }
+    __device__ static void to_si(const double *p, const KConst &K, const double (&sc)[NC],
+                                 double szc, double *g) {
+        const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        const double be = K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k;
+        g[0] = szc * 1e9;
+        g[1] = sc[0] * bh / p[1];
+        g[2] = sc[1] * be / p[2];
+        g[3] = sc[2] * 1e9;
+        g[4] = sc[0] * bh / p[4] + sc[1] * be / (2.0 * p[4]);
+    }
 };
 
 // Lennard-Jones type: BL / d [(r0/d)^n - (r0/d)^m], BL = G eps n m / (n - m) / (k 1e-18).
@@ -138,6 +166,33 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
     template <bool BF> __device__ inline R add(R d, R, R b) const {
         const R ls = lr0 - Ops<R>::log2(d);
         return Ops<R>::fma(BL * Ops<R>::rcp(d), Ops<R>::exp2(n * ls) - Ops<R>::exp2(m * ls), b);
+    }
+
+    // constants c = (BL, lr0, n, m)
+    static constexpr int NC = 4;
+    __device__ inline R grad(R d, R, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        const R r = Ops<R>::rcp(d);
+        const R ls = lr0 - Ops<R>::log2(d);
+        const R En = Ops<R>::exp2(n * ls), Em = Ops<R>::exp2(m * ls);
+        const R ln2 = R(0.69314718055994531);
+        const R Br = BL * r;
+        Fd = -Br * r * ((n + R(1)) * En - (m + R(1)) * Em);
+        Fdd = R(0);
+        dc[0] = r * (En - Em);
+        dc[1] = Br * ln2 * (n * En - m * Em);
+        dc[2] = Br * ln2 * ls * En;
+        dc[3] = -Br * ln2 * ls * Em;
+        return Br * (En - Em);
+    }
+    __device__ static void to_si(const double *p, const KConst &K, const double (&sc)[NC],
+                                 double szc, double *g) {
+        const double eps = p[1], r0 = p[2], n_ = p[3], m_ = p[4];
+        const double bl = K.G * eps * n_ * m_ / (n_ - m_) / (K.k * 1e-18);
+        g[0] = szc * 1e9;
+        g[1] = sc[0] * bl / eps;
+        g[2] = sc[1] / (r0 * 0.69314718055994531);
+        g[3] = sc[2] + sc[0] * bl * (-m_ / (n_ * (n_ - m_)));
+        g[4] = sc[3] + sc[0] * bl * (n_ / (m_ * (n_ - m_)));
     }
 };
 
@@ -176,6 +231,38 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
             return f;
         }
     }
+
+    // constants c = (BH, BE, BV, a0)
+    static constexpr int NC = 4;
+    __device__ inline R grad(R d, R dd, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        const bool out = d > a0;
+        const R m = out ? d : a0;
+        const R r = Ops<R>::rcp(m);
+        const R del = out ? R(0) : a0 - d;
+        const R s = Ops<R>::sqrt(del);
+        const R r3 = BH * r * r * r;
+        // d sqrt(delta)/d delta = 1/(2 sqrt(delta)), taken as 0 on the contact boundary
+        const R hs = s > R(0) ? R(0.5) * BV * dd * Ops<R>::rcp(s) : R(0);
+        Fd = out ? R(-2) * r3 : R(-1.5) * BE * s - hs;
+        Fdd = BV * s;
+        dc[0] = r * r;
+        dc[1] = del * s;
+        dc[2] = s * dd;
+        dc[3] = out ? R(0) : R(-2) * r3 + R(1.5) * BE * s + hs;
+        return Ops<R>::fma(BH * r, r, s * (BE * del + BV * dd));
+    }
+    __device__ static void to_si(const double *p, const KConst &K, const double (&sc)[NC],
+                                 double szc, double *g) {
+        const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        const double be = K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k;
+        const double bv = -K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k;
+        g[0] = szc * 1e9;
+        g[1] = sc[0] * bh / p[1];
+        g[2] = sc[1] * be / p[2];
+        g[3] = sc[3] * 1e9;
+        g[4] = sc[0] * bh / p[4] + sc[1] * be / (2.0 * p[4]) + sc[2] * bv / (2.0 * p[4]);
+        g[5] = sc[2] * bv / p[5];
+    }
 };
 
 // Hooke (Eq. 3): BK d for d < 0, BK = -G k_s / k.
@@ -189,6 +276,20 @@ template <typename R> struct Law<AFM_LAW_HOOKE, R> {
     }
     template <bool BF> __device__ inline R add(R d, R, R b) const {
         return d < R(0) ? Ops<R>::fma(BK, d, b) : b;
+    }
+
+    static constexpr int NC = 1;
+    __device__ inline R grad(R d, R, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        const bool in = d < R(0);
+        Fd = in ? BK : R(0);
+        Fdd = R(0);
+        dc[0] = in ? d : R(0);
+        return in ? BK * d : R(0);
+    }
+    __device__ static void to_si(const double *p, const KConst &K, const double (&sc)[NC],
+                                 double szc, double *g) {
+        g[0] = szc * 1e9;
+        g[1] = sc[0] * (-K.G / K.k);
     }
 };
 
@@ -205,6 +306,22 @@ template <typename R> struct Law<AFM_LAW_SD, R> {
     template <bool BF> __device__ inline R add(R d, R dd, R b) const {
         return d < R(0) ? Ops<R>::fma(BK, d, Ops<R>::fma(BS, dd, b)) : b;
     }
+
+    static constexpr int NC = 2;
+    __device__ inline R grad(R d, R dd, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        const bool in = d < R(0);
+        Fd = in ? BK : R(0);
+        Fdd = in ? BS : R(0);
+        dc[0] = in ? d : R(0);
+        dc[1] = in ? dd : R(0);
+        return in ? BK * d + BS * dd : R(0);
+    }
+    __device__ static void to_si(const double *p, const KConst &K, const double (&sc)[NC],
+                                 double szc, double *g) {
+        g[0] = szc * 1e9;
+        g[1] = sc[0] * (-K.G / K.k);
+        g[2] = sc[1] * (-K.G * K.wd / K.k);
+    }
 };
 
 template <typename R> struct Law<AFM_LAW_NONE, R> {
@@ -213,6 +330,18 @@ template <typename R> struct Law<AFM_LAW_NONE, R> {
     R zc;
     __device__ Law(const double *p, const KConst &) { zc = (R)(p[0] * 1e9); }
     template <bool BF> __device__ inline R add(R, R, R b) const { return b; }
+
+    static constexpr int NC = 1;  // no constants; one unused slot keeps array types valid
+    __device__ inline R grad(R, R, R &Fd, R &Fdd, R (&dc)[NC]) const {
+        Fd = R(0);
+        Fdd = R(0);
+        dc[0] = R(0);
+        return R(0);
+    }
+    __device__ static void to_si(const double *, const KConst &, const double (&)[NC], double szc,
+                                 double *g) {
+        g[0] = szc * 1e9;
+    }
 };
 
 // ------------------------------------------------------------------------------------------
@@ -225,9 +354,26 @@ struct FwdArgs {
     const int32_t *target_id;  // per trajectory or NULL
     const double *targets;     // [n_targets][W] or NULL
     int32_t n_targets;
-    int32_t group;             // > 0: n_cycles and target row are indexed by i / group
+    int32_t group;             // > 0: n_cycles and target_id are indexed by i / group
+    int32_t row_by_group;      // without target_id: target row = i / group (else row 0)
     double *amp, *phase, *J, *trace;
     int32_t *status;
+};
+
+// Adjoint launch description (see afm_grad_batch).
+struct GradArgs {
+    int64_t n, ld;
+    const double *theta;
+    const int32_t *n_cycles;
+    const int32_t *target_id;
+    const double *targets;
+    int32_t n_targets;
+    int32_t group;
+    double *J, *dJ;        // J [n], dJ [n_free][ld]
+    int32_t *status;
+    float *ckpt;           // [segments][4 NM][n] (FP64 plans: doubles)
+    float *seg;            // [kc][2 NM + 1][n]
+    int32_t kc;            // checkpoint stride in RK4 steps
 };
 
 // ------------------------------------------------------------------------------------------
@@ -251,6 +397,14 @@ struct afm_plan {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     afm::GraphCache *graph = nullptr;
+    // plan-owned workspace for afm_grad_batch and the tuned checkpoint stride per batch size
+    void *gws = nullptr;
+    size_t gws_bytes = 0;
+    int64_t tuned_n = -1;
+    int32_t tuned_kc = 0;
+    // plan-owned workspace for afm_polish
+    void *pws = nullptr;
+    size_t pws_bytes = 0;
     // PSO constants
     double pso_w, pso_c1, pso_c2, pso_vmax;
 };
@@ -271,6 +425,27 @@ hipError_t launch_pso_step(const afm_plan *plan, const afm_swarm &sw, const doub
                            hipStream_t s);
 hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double *best_theta,
                               double *best_J, int32_t *gen, hipStream_t s);
+
+// precision-explicit variants take AFM_PREC_*; the plain ones use the plan's precision
+hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s);
+hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s);
+hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
+size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
+size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
+int32_t polish_prec(const afm_plan *plan);
+
+// L-BFGS polish (lbfgs.hip)
+size_t polish_total_bytes(const afm_plan *plan, int64_t n, int32_t kc);
+hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
+                          const int32_t *target_id, const double *targets, int32_t n_targets,
+                          const int32_t *n_cycles, int32_t steps, int32_t kc, double *J_out,
+                          hipStream_t s);
+hipError_t enqueue_topk(const afm_plan *plan, const afm_swarm &sw, int32_t k, int32_t *taken,
+                        double *zsel, int32_t *tsel, const int32_t *ncyc, int32_t *nsel,
+                        hipStream_t s);
+hipError_t enqueue_merge(const afm_swarm &sw, int32_t k, const double *zsel, const double *Jsel,
+                         hipStream_t s);
+constexpr int32_t kPolishStride = 64;  // checkpoint stride of the polish's gradients
 
 // argument checks shared by the entry points
 afm_status check_forward_args(const afm_plan *plan, int64_t n, const double *theta);

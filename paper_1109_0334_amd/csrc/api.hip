@@ -55,6 +55,8 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     if (!(pr.k > 0) || !(pr.f0 > 0) || !(pr.drive_freq > 0) || !(pr.free_amplitude > 0))
         return fail(AFM_ERR_INVALID, "k, f0, drive_freq and free_amplitude must be positive");
     if (pr.ic != AFM_IC_FREE_STEADY && pr.ic != AFM_IC_REST) return fail(AFM_ERR_INVALID, "unknown ic");
+    if (pr.polish_precision < AFM_POLISH_PLAN || pr.polish_precision > AFM_POLISH_FP64)
+        return fail(AFM_ERR_INVALID, "unknown polish_precision");
     for (int i = 0; i < pr.n_modes; ++i)
         if (!(pr.q[i] > 0) || !(pr.ratio[i] > 0) || !std::isfinite(pr.gain[i]))
             return fail(AFM_ERR_INVALID, "mode quality factors and ratios must be positive");
@@ -130,6 +132,14 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
 
 void release_graph(afm_plan *plan);  // invert.hip
 
+int32_t polish_prec(const afm_plan *plan) {
+    switch (plan->prob.polish_precision) {
+    case AFM_POLISH_MIXED: return AFM_PREC_MIXED;
+    case AFM_POLISH_FP64: return AFM_PREC_FP64;
+    default: return plan->precision;
+    }
+}
+
 }  // namespace afm
 
 using namespace afm;
@@ -183,6 +193,8 @@ afm_status afm_plan_destroy(afm_plan *plan) {
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
     release_graph(plan);
     if (plan->ws) (void)hipFree(plan->ws);
+    if (plan->gws) (void)hipFree(plan->gws);
+    if (plan->pws) (void)hipFree(plan->pws);
     if (plan->d_drive_f) (void)hipFree(plan->d_drive_f);
     if (plan->d_drive_d) (void)hipFree(plan->d_drive_d);
     if (plan->d_lock) (void)hipFree(plan->d_lock);
@@ -233,6 +245,30 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_misfit launch");
 }
 
+static afm_status ensure_grad_ws(afm_plan *plan, size_t bytes) {
+    if (plan->gws_bytes >= bytes) return AFM_OK;
+    if (plan->gws) (void)hipFree(plan->gws);  // hipFree waits for work still using it
+    plan->gws = nullptr;
+    plan->gws_bytes = 0;
+    if (hipMalloc(&plan->gws, bytes) != hipSuccess)
+        return fail(AFM_ERR_NOMEM, "afm_grad_batch: workspace allocation failed");
+    plan->gws_bytes = bytes;
+    return AFM_OK;
+}
+
+
+static afm_status run_grad(afm_plan *plan, GradArgs a, int32_t kc, hipStream_t s) {
+    const size_t cb = grad_ckpt_bytes(plan, plan->precision, a.n, kc);
+    const size_t sb = grad_seg_bytes(plan, plan->precision, a.n, kc);
+    afm_status st = ensure_grad_ws(plan, cb + ((sb + 255) & ~(size_t)255) + 256);
+    if (st != AFM_OK) return st;
+    a.kc = kc;
+    a.seg = (float *)plan->gws;
+    a.ckpt = (float *)((char *)plan->gws + ((sb + 255) & ~(size_t)255));
+    hipError_t e = launch_grad(plan, a, s);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_grad_batch launch");
+}
+
 static afm_status check_swarm(const afm_plan *plan, const afm_swarm *sw) {
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     if (!sw) return fail(AFM_ERR_INVALID, "swarm is NULL");
@@ -245,6 +281,84 @@ static afm_status check_swarm(const afm_plan *plan, const afm_swarm *sw) {
         !sw->gen_to_cutoff || !sw->theta)
         return fail(AFM_ERR_INVALID, "swarm array is NULL");
     return AFM_OK;
+}
+
+afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
+                          const int32_t *target_id, const double *targets, int32_t n_targets,
+                          double *J, double *dJ, int32_t ckpt_stride, int32_t *status,
+                          afm_stream_t stream) {
+    afm_status st = check_forward_args(plan, n, theta);
+    if (st != AFM_OK) return st;
+    if (n > 0 && (!targets || !J || !status || (plan->prob.n_free > 0 && !dJ)))
+        return fail(AFM_ERR_INVALID, "targets, J, dJ and status are required");
+    if (n > 0 && n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");
+    if (ckpt_stride < 0) return fail(AFM_ERR_INVALID, "ckpt_stride < 0");
+    if (n == 0) return AFM_OK;
+    GradArgs a{};
+    a.n = n;
+    a.ld = n;
+    a.theta = theta;
+    a.n_cycles = n_cycles;
+    a.target_id = target_id;
+    a.targets = targets;
+    a.n_targets = n_targets;
+    a.J = J;
+    a.dJ = dJ;
+    a.status = status;
+    hipStream_t s = (hipStream_t)stream;
+    if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, s);
+    if (plan->tuned_n == n && plan->tuned_kc > 0) return run_grad(plan, a, plan->tuned_kc, s);
+    // autotune: time each candidate stride on this call's inputs, keep the fastest
+    const int32_t cand[3] = {16, 64, 256};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(AFM_ERR_HIP, "afm_grad_batch: event creation failed");
+    float best_ms = 0;
+    int32_t best = cand[1];
+    for (int c = 0; c < 3; ++c) {
+        (void)hipEventRecord(e0, s);
+        st = run_grad(plan, a, cand[c], s);
+        if (st != AFM_OK) break;
+        (void)hipEventRecord(e1, s);
+        float ms = 0;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = fail(AFM_ERR_HIP, "afm_grad_batch: timing failed");
+            break;
+        }
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != AFM_OK) return st;
+    plan->tuned_n = n;
+    plan->tuned_kc = best;
+    return AFM_OK;  // the last candidate's results are in the outputs
+}
+
+afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cycles,
+                      const int32_t *target_id, const double *targets, int32_t n_targets,
+                      int32_t steps, double *J, afm_stream_t stream) {
+    if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
+    if (n < 0 || steps < 0) return fail(AFM_ERR_INVALID, "n and steps must be >= 0");
+    if (plan->prob.n_free < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
+    if (n == 0) return AFM_OK;
+    if (!z || !targets || !J) return fail(AFM_ERR_INVALID, "z, targets and J are required");
+    if (n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");
+    const size_t bytes = polish_total_bytes(plan, n, kPolishStride);
+    if (plan->pws_bytes < bytes) {
+        if (plan->pws) (void)hipFree(plan->pws);
+        plan->pws = nullptr;
+        plan->pws_bytes = 0;
+        if (hipMalloc(&plan->pws, bytes) != hipSuccess)
+            return fail(AFM_ERR_NOMEM, "afm_polish: workspace allocation failed");
+        plan->pws_bytes = bytes;
+    }
+    hipError_t e = enqueue_polish(plan, plan->pws, n, z, target_id, targets, n_targets, n_cycles,
+                                  steps, kPolishStride, J, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_polish launch");
 }
 
 afm_status afm_swarm_init(afm_plan *plan, afm_swarm *swarm, uint64_t seed, afm_stream_t stream) {

@@ -1,0 +1,409 @@
+// grad.hip -- discrete adjoint of the RK4 trajectory and window misfit (afm_grad_batch).
+//
+// The paper inverts with a gradient-free swarm (Sec. 3.4); its misfit J (Eq. 5) is nonetheless a
+// smooth function of the force parameters along most of the search box, so its exact gradient is
+// used here to polish swarm optima.  The gradient is that of the discrete map the forward kernel
+// computes: reverse-mode differentiation of the classical RK4 steps (stages reversed in the
+// order 4, 3, 2, 1) and of the window misfit.
+//
+// One lane owns one trajectory.  Forward pass: integrate as the forward kernel does, writing the
+// full FP32 state (including the Kahan residuals) to an HBM checkpoint every `kc` steps.
+// Reverse sweep, segment by segment from the end: reload the checkpoint, recompute the
+// segment's states with the forward code (bit-identical) into a segment buffer, then walk the
+// segment backwards applying the transposed stage Jacobians.  The adjoint state is FP32; the
+// sensitivities to the law's constants are summed over a step's four stages in FP32 and
+// accumulated across steps in FP64 (so the result is independent of the checkpoint stride), and
+// are mapped to SI parameter derivatives by the chain rule at the end.
+// Buffers are structure-of-arrays over lanes ([slot][variable][n]) so every access coalesces.
+#include "rk4.hpp"
+
+namespace afm {
+
+namespace {
+
+// dJ contributions of one stage: kb = adjoint of the stage slope k = f(Y).  Adds
+// (df/dy)^T kb to Yb, and (dF/dc)^T S, (dF/dd)^T S to the constant and z_c sensitivities.
+template <int NM, class L, typename R>
+__device__ __forceinline__ void stage_vjp(const R (&kbx)[NM], const R (&kbv)[NM], R Fd, R Fdd,
+                                          const R (&dc)[L::NC], const R (&om2)[NM],
+                                          const R (&cd)[NM], R (&Ybx)[NM], R (&Ybv)[NM],
+                                          R (&gsf)[L::NC], R &gzf) {
+    R S = kbv[0];
+#pragma unroll
+    for (int i = 1; i < NM; ++i) S += kbv[i];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        Ybx[i] = Ops<R>::fma(-om2[i], kbv[i], Fd * S);
+        Ybv[i] = Ops<R>::fma(-cd[i], kbv[i], Ops<R>::fma(Fdd, S, kbx[i]));
+    }
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) gsf[k] = Ops<R>::fma(S, dc[k], gsf[k]);
+    gzf = Ops<R>::fma(S, Fd, gzf);
+}
+
+// Slopes at a stage state (x = gap for mode 1), with the force partials for the adjoint.
+template <int NM, class L, typename R>
+__device__ __forceinline__ void stage_eval(const L &law, const R (&x)[NM], const R (&v)[NM],
+                                           const R (&om2)[NM], const R (&cd)[NM],
+                                           const R (&gn)[NM], R D, R (&a)[NM], R &Fd, R &Fdd,
+                                           R (&dc)[L::NC]) {
+    R d = x[0];
+#pragma unroll
+    for (int i = 1; i < NM; ++i) d += x[i];
+    R dd = v[0];
+#pragma unroll
+    for (int i = 1; i < NM; ++i) dd += v[i];
+    const R F = law.grad(d, dd, Fd, Fdd, dc);
+    if constexpr (NM == 1) {
+        a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc, Ops<R>::fma(-cd[0], v[0], F + D));
+    } else {
+        a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc, Ops<R>::fma(-cd[0], v[0], Ops<R>::fma(gn[0], D, F)));
+#pragma unroll
+        for (int i = 1; i < NM; ++i)
+            a[i] = Ops<R>::fma(-om2[i], x[i], Ops<R>::fma(-cd[i], v[i], Ops<R>::fma(gn[i], D, F)));
+    }
+}
+
+// Reverse one RK4 step y_n -> y_{n+1}: on entry (xb, vb) = dJ/dy_{n+1}, on exit dJ/dy_n.
+template <int NM, class L, typename R>
+__device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], const R (&v)[NM],
+                                             R (&xb)[NM], R (&vb)[NM], const R (&om2)[NM],
+                                             const R (&cd)[NM], const R (&gn)[NM], R h, R h2,
+                                             R h3, R h6, R D0, R D1, R D2, R (&gsf)[L::NC],
+                                             R &gzf) {
+    // recompute the four stage states and the force partials there
+    R a1[NM], a2[NM], a3[NM], a4[NM], Y[NM], V2[NM], V3[NM], V4[NM];
+    R Fd1, Fdd1, Fd2, Fdd2, Fd3, Fdd3, Fd4, Fdd4;
+    R dc1[L::NC], dc2[L::NC], dc3[L::NC], dc4[L::NC];
+    stage_eval<NM>(law, x, v, om2, cd, gn, D0, a1, Fd1, Fdd1, dc1);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        Y[i] = Ops<R>::fma(h2, v[i], x[i]);
+        V2[i] = Ops<R>::fma(h2, a1[i], v[i]);
+    }
+    stage_eval<NM>(law, Y, V2, om2, cd, gn, D1, a2, Fd2, Fdd2, dc2);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        Y[i] = Ops<R>::fma(h2, V2[i], x[i]);
+        V3[i] = Ops<R>::fma(h2, a2[i], v[i]);
+    }
+    stage_eval<NM>(law, Y, V3, om2, cd, gn, D1, a3, Fd3, Fdd3, dc3);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        Y[i] = Ops<R>::fma(h, V3[i], x[i]);
+        V4[i] = Ops<R>::fma(h, a3[i], v[i]);
+    }
+    stage_eval<NM>(law, Y, V4, om2, cd, gn, D2, a4, Fd4, Fdd4, dc4);
+    // stage adjoints: kb_i = h (b_i yb + a_{i+1,i} Yb_{i+1})
+    R kbx[NM], kbv[NM], Ybx[NM], Ybv[NM], sx[NM], sv[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        kbx[i] = h6 * xb[i];
+        kbv[i] = h6 * vb[i];
+    }
+    stage_vjp<NM, L>(kbx, kbv, Fd4, Fdd4, dc4, om2, cd, Ybx, Ybv, gsf, gzf);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx[i] = Ybx[i];
+        sv[i] = Ybv[i];
+        kbx[i] = Ops<R>::fma(h3, xb[i], h * Ybx[i]);
+        kbv[i] = Ops<R>::fma(h3, vb[i], h * Ybv[i]);
+    }
+    stage_vjp<NM, L>(kbx, kbv, Fd3, Fdd3, dc3, om2, cd, Ybx, Ybv, gsf, gzf);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx[i] += Ybx[i];
+        sv[i] += Ybv[i];
+        kbx[i] = Ops<R>::fma(h3, xb[i], h2 * Ybx[i]);
+        kbv[i] = Ops<R>::fma(h3, vb[i], h2 * Ybv[i]);
+    }
+    stage_vjp<NM, L>(kbx, kbv, Fd2, Fdd2, dc2, om2, cd, Ybx, Ybv, gsf, gzf);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx[i] += Ybx[i];
+        sv[i] += Ybv[i];
+        kbx[i] = Ops<R>::fma(h6, xb[i], h2 * Ybx[i]);
+        kbv[i] = Ops<R>::fma(h6, vb[i], h2 * Ybv[i]);
+    }
+    stage_vjp<NM, L>(kbx, kbv, Fd1, Fdd1, dc1, om2, cd, Ybx, Ybv, gsf, gzf);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        xb[i] += sx[i] + Ybx[i];
+        vb[i] += sv[i] + Ybv[i];
+    }
+}
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr bool COMP = MIXED;
+    constexpr int NS = 4 * NM;      // checkpointed scalars: x, v, cx, cv
+    constexpr int NB = 2 * NM + 1;  // segment-buffer scalars: x, v, dJ/du of the next state
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double p[kMaxParams];
+#pragma unroll
+    for (int q = 0; q < kMaxParams; ++q) {
+        p[q] = K.params[q];
+#pragma unroll
+        for (int j = 0; j < kMaxParams; ++j)
+            if (j < K.n_free && K.free_index[j] == q) p[q] = A.theta[(int64_t)j * A.ld + i];
+    }
+    const L law(p, K);
+    const double zc = p[0] * 1e9;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int N = K.N;
+    const int64_t W = (int64_t)K.lockin * N;
+    const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : 0;
+    const int kc = A.kc;
+    const int64_t n_lanes = A.n;
+    auto fail = [&](int32_t st) {
+        A.J[i] = INFINITY;
+        for (int j = 0; j < K.n_free; ++j) A.dJ[(int64_t)j * A.ld + i] = NAN;
+        A.status[i] = st;
+    };
+    if (nc < K.lockin || nc > K.n_cycles || row < 0 || row >= A.n_targets) {
+        fail(AFM_ST_BAD_INPUT);
+        return;
+    }
+    const double *__restrict__ Urow = A.targets + row * W;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+
+    R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        x[m] = (R)(m == 0 ? zc + K.y0[0] : K.y0[m]);
+        v[m] = (R)K.y0[NM + m];
+        cx[m] = R(0);
+        cv[m] = R(0);
+        om2[m] = (R)K.om2[m];
+        cd[m] = (R)K.cdamp[m];
+        gn[m] = (R)K.gain[m];
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h3 = (R)(K.h / 3.0), h6 = (R)(K.h / 6.0);
+    float *__restrict__ ck = A.ckpt;
+    float *__restrict__ sg = A.seg;
+    auto put = [&](float *base, int64_t slot, int var, int nvar, R val) {
+        base[(slot * nvar + var) * n_lanes + i] = (float)val;
+    };
+
+    // ---- forward pass with checkpoints
+    const int64_t Ntot = (int64_t)nc * N;
+    const int64_t first_w = Ntot - W + 1;  // window = states first_w .. Ntot
+    double Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+    int64_t n = 0;
+    int cdn = 0;  // steps to the next checkpoint
+    for (int c = 0; c < nc && !st; ++c) {
+        for (int s = 0; s < N; ++s, ++n) {
+            if (cdn == 0) {
+                const int64_t slot = n / kc;
+#pragma unroll
+                for (int m = 0; m < NM; ++m) {
+                    if constexpr (MIXED) {
+                        put(ck, slot, m, NS, x[m]);
+                        put(ck, slot, NM + m, NS, v[m]);
+                        put(ck, slot, 2 * NM + m, NS, cx[m]);
+                        put(ck, slot, 3 * NM + m, NS, cv[m]);
+                    }
+                }
+                if constexpr (!MIXED) {
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) {  // FP64 state stored as two floats' worth
+                        double *ckd = reinterpret_cast<double *>(ck);
+                        ckd[(slot * NS + m) * n_lanes + i] = x[m];
+                        ckd[(slot * NS + NM + m) * n_lanes + i] = v[m];
+                    }
+                }
+                cdn = kc;
+            }
+            --cdn;
+            rk4_step<NM, COMP, true>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                     Dt[2 * s + 1], Dt[2 * s + 2]);
+            if (n + 1 >= first_w) {
+                const double u = sample<NM, COMP>(x, cx, zc);
+                const double U = Urow[n + 1 - first_w] * 1e9;
+                const double e = U - u;
+                Jn += e * e;
+                Jd += U * U;
+            }
+        }
+        bool fin = true;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) fin = fin && isfinite(x[m]) && isfinite(v[m]);
+        if (!fin) st = AFM_ST_NONFINITE;
+        else if (fabs(sample<NM, COMP>(x, cx, zc)) > K.div_nm) st = AFM_ST_DIVERGED;
+    }
+    const double J = Jn / Jd;
+    if (st || !isfinite(J)) {
+        fail(st ? st : AFM_ST_NONFINITE);
+        return;
+    }
+    const double coef = -2.0 / Jd;  // dJ/du_n = coef (U_n - u_n)
+
+    // ---- reverse sweep
+    R xb[NM], vb[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        xb[m] = R(0);
+        vb[m] = R(0);
+    }
+    double gs[L::NC];
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) gs[k] = 0.0;
+    double gz = 0.0;
+    const int64_t nseg = (Ntot + kc - 1) / kc;
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int64_t n0 = sgi * kc;
+        const int64_t n1 = n0 + kc < Ntot ? n0 + kc : Ntot;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            if constexpr (MIXED) {
+                x[m] = ck[(sgi * NS + m) * n_lanes + i];
+                v[m] = ck[(sgi * NS + NM + m) * n_lanes + i];
+                cx[m] = ck[(sgi * NS + 2 * NM + m) * n_lanes + i];
+                cv[m] = ck[(sgi * NS + 3 * NM + m) * n_lanes + i];
+            } else {
+                const double *ckd = reinterpret_cast<const double *>(ck);
+                x[m] = ckd[(sgi * NS + m) * n_lanes + i];
+                v[m] = ckd[(sgi * NS + NM + m) * n_lanes + i];
+            }
+        }
+        // recompute the segment, keeping y_n and dJ/du_{n+1}
+        int s = (int)(n0 % N);
+        for (int64_t q = n0; q < n1; ++q) {
+            const int64_t k = q - n0;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                if constexpr (MIXED) {
+                    put(sg, k, m, NB, x[m]);
+                    put(sg, k, NM + m, NB, v[m]);
+                } else {
+                    double *sgd = reinterpret_cast<double *>(sg);
+                    sgd[(k * NB + m) * n_lanes + i] = x[m];
+                    sgd[(k * NB + NM + m) * n_lanes + i] = v[m];
+                }
+            }
+            rk4_step<NM, COMP, true>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                     Dt[2 * s + 1], Dt[2 * s + 2]);
+            if (q + 1 >= first_w) {
+                const double u = sample<NM, COMP>(x, cx, zc);
+                const double ub = coef * (Urow[q + 1 - first_w] * 1e9 - u);
+                if constexpr (MIXED) put(sg, k, 2 * NM, NB, (R)ub);
+                else reinterpret_cast<double *>(sg)[(k * NB + 2 * NM) * n_lanes + i] = ub;
+            }
+            s = s + 1 == N ? 0 : s + 1;
+        }
+        // walk the segment backwards; a step's four stage contributions are summed in R and
+        // flushed to FP64 every step, so the result does not depend on the stride
+        s = (int)((n1 - 1) % N);
+        for (int64_t q = n1 - 1; q >= n0; --q) {
+            const int64_t k = q - n0;
+            R yx[NM], yv[NM];
+            if (q + 1 >= first_w) {
+                R ub;
+                if constexpr (MIXED) ub = sg[(k * NB + 2 * NM) * n_lanes + i];
+                else ub = reinterpret_cast<const double *>(sg)[(k * NB + 2 * NM) * n_lanes + i];
+#pragma unroll
+                for (int m = 0; m < NM; ++m) xb[m] += ub;
+            }
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                if constexpr (MIXED) {
+                    yx[m] = sg[(k * NB + m) * n_lanes + i];
+                    yv[m] = sg[(k * NB + NM + m) * n_lanes + i];
+                } else {
+                    const double *sgd = reinterpret_cast<const double *>(sg);
+                    yx[m] = sgd[(k * NB + m) * n_lanes + i];
+                    yv[m] = sgd[(k * NB + NM + m) * n_lanes + i];
+                }
+            }
+            R gsf[L::NC];
+#pragma unroll
+            for (int k = 0; k < L::NC; ++k) gsf[k] = R(0);
+            R gzf = R(0);
+            reverse_step<NM, L>(law, yx, yv, xb, vb, om2, cd, gn, h, h2, h3, h6, Dt[2 * s],
+                                Dt[2 * s + 1], Dt[2 * s + 2], gsf, gzf);
+#pragma unroll
+            for (int k = 0; k < L::NC; ++k) gs[k] += (double)gsf[k];
+            gz += (double)gzf;
+            s = s == 0 ? N - 1 : s - 1;
+        }
+    }
+    // the initial state does not depend on the law parameters
+    double g[kMaxParams];
+#pragma unroll
+    for (int q = 0; q < kMaxParams; ++q) g[q] = 0.0;
+    L::to_si(p, K, gs, gz, g);
+    A.J[i] = J;
+    for (int j = 0; j < K.n_free; ++j) {
+        double gj = 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxParams; ++q)
+            if (K.free_index[j] == q) gj = g[q];
+        A.dJ[(int64_t)j * A.ld + i] = gj;
+    }
+    A.status[i] = 0;
+}
+
+template <int LAW, int NM, bool MIXED>
+hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
+    const int block = 64;
+    const int64_t grid = (a.n + block - 1) / block;
+    hipLaunchKernelGGL((k_grad<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0, s, a, K);
+    return hipGetLastError();
+}
+
+template <int LAW, bool MIXED>
+hipError_t launch_modes(const GradArgs &a, const KConst &K, hipStream_t s) {
+    switch (K.nm) {
+    case 1: return launch_t<LAW, 1, MIXED>(a, K, s);
+    case 2: return launch_t<LAW, 2, MIXED>(a, K, s);
+    case 3: return launch_t<LAW, 3, MIXED>(a, K, s);
+    case 4: return launch_t<LAW, 4, MIXED>(a, K, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <bool MIXED>
+hipError_t launch_law(const GradArgs &a, const KConst &K, hipStream_t s) {
+    switch (K.law) {
+    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(a, K, s);
+    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(a, K, s);
+    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(a, K, s);
+    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(a, K, s);
+    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(a, K, s);
+    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(a, K, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc) {
+    const KConst &K = plan->kc;
+    const size_t esz = prec == AFM_PREC_MIXED ? sizeof(float) : sizeof(double);
+    const int64_t nseg = ((int64_t)K.n_cycles * K.N + kc - 1) / kc;
+    return (size_t)nseg * 4 * K.nm * (size_t)n * esz;
+}
+
+size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc) {
+    const size_t esz = prec == AFM_PREC_MIXED ? sizeof(float) : sizeof(double);
+    return (size_t)kc * (2 * plan->kc.nm + 1) * (size_t)n * esz;
+}
+
+hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (prec == AFM_PREC_MIXED) return launch_law<true>(a, plan->kc, s);
+    return launch_law<false>(a, plan->kc, s);
+}
+
+hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s) {
+    return launch_grad_p(plan, plan->precision, a, s);
+}
+
+}  // namespace afm

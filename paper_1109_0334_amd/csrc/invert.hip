@@ -12,7 +12,7 @@ namespace afm {
 struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int32_t S = 0, P = 0, T = 0;
+    int32_t S = 0, P = 0, T = 0, lb_steps = 0, lb_k = 0;
     uint64_t seed = 0;
     double cutoff = 0;
     const double *targets = nullptr;
@@ -35,11 +35,12 @@ namespace {
 struct WsLayout {
     size_t bytes;
     size_t z, v, pbest_z, theta, pbest_J, J, gbest_z, gbest_J, gen, status;
+    size_t taken, zsel, tsel, nsel, Jsel, polish;  // polish of the top-k (if requested)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-WsLayout layout(int32_t D, int32_t S, int32_t P) {
+WsLayout layout(const afm_plan *plan, int32_t D, int32_t S, int32_t P, int32_t k) {
     const size_t n = (size_t)S * P;
     WsLayout L{};
     size_t off = 0;
@@ -58,6 +59,15 @@ WsLayout layout(int32_t D, int32_t S, int32_t P) {
     L.gbest_J = take(sizeof(double) * S);
     L.gen = take(sizeof(int32_t) * S);
     L.status = take(sizeof(int32_t) * n);
+    if (k > 0) {
+        const size_t m = (size_t)S * k;
+        L.taken = take(sizeof(int32_t) * n);
+        L.zsel = take(sizeof(double) * D * m);
+        L.tsel = take(sizeof(int32_t) * m);
+        L.nsel = take(sizeof(int32_t) * m);
+        L.Jsel = take(sizeof(double) * m);
+        L.polish = take(polish_total_bytes(plan, (int64_t)m, kPolishStride));
+    }
     L.bytes = off;
     return L;
 }
@@ -84,8 +94,9 @@ using namespace afm;
 
 extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
                                  const int32_t *n_cycles, int32_t particles, int32_t iters,
-                                 uint64_t seed, double cutoff, double *best_theta,
-                                 double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream) {
+                                 uint64_t seed, double cutoff, int32_t lbfgs_steps,
+                                 int32_t lbfgs_topk, double *best_theta, double *best_J,
+                                 int32_t *gen_to_cutoff, afm_stream_t stream) {
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     const int32_t D = plan->prob.n_free;
     if (D < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
@@ -94,7 +105,10 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     if ((int64_t)n_swarms * particles > (int64_t)1 << 31) return fail(AFM_ERR_INVALID, "swarm too large");
     if (!targets || !best_theta || !best_J || !gen_to_cutoff)
         return fail(AFM_ERR_INVALID, "targets and outputs are required");
-    const WsLayout L = layout(D, n_swarms, particles);
+    if (lbfgs_steps < 0 || lbfgs_topk < 0 || lbfgs_topk > particles)
+        return fail(AFM_ERR_INVALID, "need 0 <= lbfgs_steps and 0 <= lbfgs_topk <= particles");
+    const int32_t kpol = lbfgs_steps > 0 ? lbfgs_topk : 0;
+    const WsLayout L = layout(plan, D, n_swarms, particles, kpol);
     afm_status st = ensure_workspace(plan, L.bytes);
     if (st != AFM_OK) return st;
     char *ws = (char *)plan->ws;
@@ -117,7 +131,7 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     const bool hit = g && g->S == n_swarms && g->P == particles && g->T == iters && g->seed == seed &&
                      g->cutoff == cutoff && g->targets == targets && g->ncyc == n_cycles &&
                      g->best_theta == best_theta && g->best_J == best_J && g->gen == gen_to_cutoff &&
-                     g->ws == plan->ws;
+                     g->ws == plan->ws && g->lb_steps == lbfgs_steps && g->lb_k == kpol;
     hipError_t e;
     if (!hit) {
         release_graph(plan);
@@ -134,12 +148,25 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         a.targets = targets;
         a.n_targets = n_swarms;
         a.group = particles;
+        a.row_by_group = 1;
         a.J = J;
         a.status = status;
         for (int32_t t = 0; t < iters && e == hipSuccess; ++t) {
             e = launch_forward(plan, a, plan->stream);
             if (e == hipSuccess)
                 e = launch_pso_step(plan, sw, J, seed, t, t == iters - 1, cutoff, plan->stream);
+        }
+        if (e == hipSuccess && kpol > 0) {
+            const int64_t m = (int64_t)n_swarms * kpol;
+            double *zsel = (double *)(ws + L.zsel), *Jsel = (double *)(ws + L.Jsel);
+            int32_t *tsel = (int32_t *)(ws + L.tsel), *nsel = (int32_t *)(ws + L.nsel);
+            e = enqueue_topk(plan, sw, kpol, (int32_t *)(ws + L.taken), zsel, tsel, n_cycles, nsel,
+                             plan->stream);
+            if (e == hipSuccess)
+                e = enqueue_polish(plan, ws + L.polish, m, zsel, tsel, targets, n_swarms,
+                                   n_cycles ? nsel : nullptr, lbfgs_steps, kPolishStride, Jsel,
+                                   plan->stream);
+            if (e == hipSuccess) e = enqueue_merge(sw, kpol, zsel, Jsel, plan->stream);
         }
         if (e == hipSuccess) e = launch_gather_best(plan, sw, best_theta, best_J, gen_to_cutoff, plan->stream);
         hipGraph_t graph = nullptr;
@@ -166,6 +193,8 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         g->best_J = best_J;
         g->gen = gen_to_cutoff;
         g->ws = plan->ws;
+        g->lb_steps = lbfgs_steps;
+        g->lb_k = kpol;
     }
     // order the replay after the caller's earlier work and the caller's later work after it
     e = hipEventRecord(plan->ev_in, (hipStream_t)stream);

@@ -44,9 +44,10 @@ _LAYOUT_PROBE = r"""
 #include <stdio.h>
 #include "afm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
          offsetof(afm_problem, params), offsetof(afm_problem, n_free),
-         offsetof(afm_problem, lo), offsetof(afm_problem, pso_w), sizeof(afm_swarm));
+         offsetof(afm_problem, lo), offsetof(afm_problem, pso_w),
+         offsetof(afm_problem, polish_precision), sizeof(afm_swarm));
   printf("%zu %zu\n", offsetof(afm_swarm, z), offsetof(afm_swarm, theta));
   return 0;
 }
@@ -64,7 +65,7 @@ def test_binding_struct_layout_matches_header(afm, tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P, S = afm._Problem, afm._Swarm
     expect = [C.sizeof(P), P.k.offset, P.params.offset, P.n_free.offset, P.lo.offset,
-              P.pso_w.offset, C.sizeof(S), S.z.offset, S.theta.offset]
+              P.pso_w.offset, P.polish_precision.offset, C.sizeof(S), S.z.offset, S.theta.offset]
     assert [int(x) for x in out] == expect
 
 
