@@ -12,7 +12,9 @@ sums, noisy synthetic target (sigma 0.05 nm) made by the plain FP64 GPU path at 
 
 Prints one JSON line (metric RK4 steps/s).  Also reported: inversions/s (200 generations per
 inversion), the plain FP64 GPU path on the same workload, the forward kernel's roofline (FP32
-VALU), the same kernel on a GPU-filling batch, and the oracle timed on one host core.
+VALU), the same kernel on a GPU-filling batch, the uneven pixel-batch workload (4096 pixel
+inversions with per-pixel separation, stiffness and period count, through the persistent
+work-queue kernel), and the oracle timed on one host core.
 """
 from __future__ import annotations
 
@@ -44,7 +46,72 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP64 and saturated legs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-pixels", action="store_true", help="skip the uneven pixel-batch leg")
+    ap.add_argument("--pixel-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def pixel_leg(afm, W, dev, steps):
+    """Uneven batching: 4096 pixel inversions of (H, E*) with per-pixel E*, set-point and period
+    count (100..2000), 128 particles, through the persistent work-queue kernel."""
+    import numpy as np
+    import torch
+
+    from paper_1109_0334_amd import setpoint
+
+    cfg = W.config("c3")
+    m = cfg["model"]
+    pix = W.pixels(cfg)
+    S, P = int(cfg["pixels"]), int(cfg["particles"])
+    N, Wn = m["steps_per_cycle"], m["lockin_cycles"] * m["steps_per_cycle"]
+    base = W.full_params(cfg)
+    t0 = time.perf_counter()
+    zc = setpoint.separations(afm, m, base, [2], [pix["Estar"]], pix["setpoint"], device=dev)
+    t_sep = time.perf_counter() - t0
+    good = np.isfinite(zc)
+    sp = np.tile(base[:, None], (1, S)).astype(np.float64)
+    sp = np.concatenate([sp, np.zeros((8 - sp.shape[0], S))], axis=0)
+    sp[0] = np.where(good, zc, base[0])
+    sp[2] = pix["Estar"]
+    # targets: plain FP64 forward at each pixel's truth over its own period count
+    ref = afm.Plan(m, base, [(0, 0.0, 1.0, 0), (2, 0.0, 1.0, 0)], precision="fp64", device=dev)
+    th = torch.tensor(np.stack([sp[0], sp[2]]), device=dev)
+    cyc = torch.tensor(pix["cycles"], device=dev)
+    U = ref.forward_batch(th, n_cycles=cyc, trace=True)["trace"].contiguous()
+    free = W.free_index(cfg)
+    plan = afm.Plan(m, base, free, precision="mixed", device=dev)
+    spd = torch.tensor(sp, device=dev)
+    plan.invert(U, P, 1, seed=0, n_cycles=cyc, swarm_params=spd)
+    torch.cuda.synchronize()
+    plan.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rk4 = float(P) * float(np.sum(pix["cycles"])) * N * steps
+    # the same misfits as one plain-grid launch (per-lane period counts, no queue) for contrast
+    th_all = torch.tensor(W.draw_free(cfg, S * P, 9).T.copy(), device=dev)
+    tid = torch.arange(S, device=dev, dtype=torch.int32).repeat_interleave(P)
+    ncl = cyc.repeat_interleave(P)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.misfit(th_all, U, target_id=tid, n_cycles=ncl)
+    e1.record()
+    torch.cuda.synchronize()
+    grid_ms = e0.elapsed_time(e1)
+    sat = FLOPS_PER_STEP_DMT1 * rk4 / dt
+    return {"workload": "c3-uneven: 4096 pixels x 128 particles, DMT, invert (H, log E*), "
+                        "periods U{100..2000} x 256 steps, per-pixel E* and set-point",
+            "generations": steps, "ms_per_generation": dt / steps * 1e3,
+            "rk4_steps_per_s": rk4 / dt, "inversions_per_s": S / (dt / steps * cfg["iters"]),
+            "achieved_tflops": sat / 1e12, "frac_published_peak": sat / PEAK_FP32_PUBLISHED,
+            "frac_scalar_issue_peak": sat / PEAK_FP32_SCALAR_ISSUE,
+            "plain_grid_forward_ms": grid_ms, "setup_separation_s": t_sep,
+            "pixels_without_setpoint_crossing": int((~good).sum()),
+            "median_best_J": float(np.median(out["best_J"].cpu().numpy()))}
 
 
 def cpu_baseline(cfg, seconds):
@@ -89,6 +156,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "reps": 3}))
+        return
     cfg = W.config("c2")
     m = cfg["model"]
     P = cfg["particles"]
@@ -190,6 +265,8 @@ def main():
         "roofline": roof,
     }
     line.update(extras)
+    if not args.no_pixels:
+        line["uneven_pixels"] = pixel_leg(afm, W, dev, max(1, args.pixel_steps))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -187,12 +187,14 @@ afm_status afm_pso_step(afm_plan *plan, afm_swarm *swarm, const double *J, uint6
  * normalised coordinates of the problem's search box: history 5, H0 = s'y / y'y, trial steps
  * 2^-k (k = 0..20) of the direction evaluated together, the first satisfying Armijo (c = 1e-4)
  * accepted, a pair dropped when s'y <= 1e-12 |s||y|; a point with no acceptable step stops.
- * z: [n_free][n] normalised positions (device, in/out); n_cycles, target_id, targets,
- * n_targets as in afm_misfit; J: [n] misfit at the returned positions (device).  Workspace is
- * owned by the plan.  Enqueues a fixed sequence of launches (no host synchronisation). */
-afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cycles,
-                      const int32_t *target_id, const double *targets, int32_t n_targets,
-                      int32_t steps, double *J, afm_stream_t stream);
+ * z: [n_free][n] normalised positions (device, in/out); params: [AFM_MAX_PARAMS][n] full
+ * parameter vectors of the points (their free entries are ignored) or NULL for the problem's;
+ * n_cycles, target_id, targets, n_targets as in afm_misfit; J: [n] misfit at the returned
+ * positions (device).  Workspace is owned by the plan.  Enqueues a fixed sequence of launches
+ * (no host synchronisation). */
+afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params,
+                      const int32_t *n_cycles, const int32_t *target_id, const double *targets,
+                      int32_t n_targets, int32_t steps, double *J, afm_stream_t stream);
 
 /* Whole inversions (IP, Sec. 2.3) of S independent targets, one swarm of P particles each, T
  * generations: init, then T x [misfit of every particle -> PSO generation]; then, if
@@ -201,9 +203,13 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cyc
  * a HIP graph and replayed without host round-trips.  targets: [S][W] (device); n_cycles: [S]
  * per-target period counts or NULL (uneven counts run through the persistent work-queue
  * kernel, longest first).  Outputs (device): best_theta [n_free][S] SI, best_J [S],
- * gen_to_cutoff [S].  lbfgs_topk <= particles.  Workspace is owned by the plan. */
+ * gen_to_cutoff [S].  swarm_params: [AFM_MAX_PARAMS][S] full parameter vectors per target
+ * (e.g. each pixel's separation from its set-point; free entries ignored) or NULL for the
+ * problem's.  lbfgs_topk <= particles.  Workspace is owned by the plan; with n_cycles the
+ * first call reads the period counts to order the work queue (a synchronous copy). */
 afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
-                      const int32_t *n_cycles, int32_t particles, int32_t iters, uint64_t seed,
+                      const int32_t *n_cycles, const double *swarm_params, int32_t particles,
+                      int32_t iters, uint64_t seed,
                       double cutoff, int32_t lbfgs_steps, int32_t lbfgs_topk, double *best_theta,
                       double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream);
 

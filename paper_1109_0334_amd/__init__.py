@@ -90,8 +90,8 @@ def lib() -> C.CDLL:
     L.afm_grad_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
     L.afm_swarm_init.argtypes = [vp, C.POINTER(_Swarm), u64, vp]
     L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
-    L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, i32, i32, vp, vp]
-    L.afm_invert.argtypes = [vp, i32, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
+    L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, vp]
+    L.afm_invert.argtypes = [vp, i32, vp, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
@@ -281,7 +281,7 @@ class Plan:
                                   int(it), int(bool(is_last)), float(cutoff), _stream()),
                "afm_pso_step")
 
-    def polish(self, z, targets, target_id=None, n_cycles=None, steps=10):
+    def polish(self, z, targets, target_id=None, n_cycles=None, steps=10, params=None):
         """L-BFGS polish of normalised positions z [n_free][n] (in place) -> J [n]."""
         import torch
 
@@ -290,13 +290,16 @@ class Plan:
         J = torch.empty(n, dtype=torch.float64, device=self.device)
         tid = _dev_i32(target_id, self.device)
         nc = _dev_i32(n_cycles, self.device)
-        _check(lib().afm_polish(self._h, n, _ptr(z), _ptr(nc), _ptr(tid), _ptr(targets),
+        pp = None if params is None else _dev_f64(params, self.device).reshape(MAX_PARAMS, n)
+        _check(lib().afm_polish(self._h, n, _ptr(z), _ptr(pp), _ptr(nc), _ptr(tid), _ptr(targets),
                                 targets.shape[0], int(steps), _ptr(J), _stream()), "afm_polish")
         return J
 
     def invert(self, targets, particles, iters, seed=0, cutoff=0.0, n_cycles=None, out=None,
-               lbfgs_steps=0, lbfgs_topk=0):
-        """S inversions (one swarm per target row) -> dict(best_theta [D][S], best_J, gen)."""
+               lbfgs_steps=0, lbfgs_topk=0, swarm_params=None):
+        """S inversions (one swarm per target row) -> dict(best_theta [D][S], best_J, gen).
+
+        swarm_params: optional [MAX_PARAMS][S] full parameter vectors per target."""
         import torch
 
         targets = _dev_f64(targets, self.device).reshape(-1, self.W)
@@ -306,8 +309,11 @@ class Plan:
                    "best_J": torch.empty(S, dtype=torch.float64, device=self.device),
                    "gen_to_cutoff": torch.empty(S, dtype=torch.int32, device=self.device)}
         nc = _dev_i32(n_cycles, self.device)
-        self._keep = (targets, nc)  # the captured graph refers to these buffers
-        _check(lib().afm_invert(self._h, S, _ptr(targets), _ptr(nc), int(particles), int(iters),
+        sp = None if swarm_params is None else \
+            _dev_f64(swarm_params, self.device).reshape(MAX_PARAMS, S)
+        self._keep = (targets, nc, sp)  # the captured graph refers to these buffers
+        _check(lib().afm_invert(self._h, S, _ptr(targets), _ptr(nc), _ptr(sp), int(particles),
+                                int(iters),
                                 int(seed) & (2**64 - 1), float(cutoff), int(lbfgs_steps),
                                 int(lbfgs_topk), _ptr(out["best_theta"]),
                                 _ptr(out["best_J"]), _ptr(out["gen_to_cutoff"]), _stream()),

@@ -358,6 +358,11 @@ struct FwdArgs {
     int32_t row_by_group;      // without target_id: target row = i / group (else row 0)
     double *amp, *phase, *J, *trace;
     int32_t *status;
+    const double *base;        // optional per-group full parameter vectors [kMaxParams][base_ld]
+    int64_t base_ld;           // (indexed by i / group, or i when group == 0)
+    const int32_t *items;      // persistent queue: item order (NULL = plain grid launch)
+    int32_t n_items, chunks;   // items = groups x chunks of 64 lanes
+    int32_t *head;             // queue head counter (reset to 0 before the launch)
 };
 
 // Adjoint launch description (see afm_grad_batch).
@@ -374,6 +379,8 @@ struct GradArgs {
     float *ckpt;           // [segments][4 NM][n] (FP64 plans: doubles)
     float *seg;            // [kc][2 NM + 1][n]
     int32_t kc;            // checkpoint stride in RK4 steps
+    const double *base;    // optional per-point full parameter vectors [kMaxParams][base_ld]
+    int64_t base_ld;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -397,6 +404,7 @@ struct afm_plan {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     afm::GraphCache *graph = nullptr;
+    int32_t n_cu = 0;               // compute units of the plan's device (persistent grids)
     // plan-owned workspace for afm_grad_batch and the tuned checkpoint stride per batch size
     void *gws = nullptr;
     size_t gws_bytes = 0;
@@ -415,6 +423,20 @@ namespace afm {
 void set_error(const std::string &msg);
 afm_status fail(afm_status code, const std::string &msg);
 afm_status hip_fail(hipError_t e, const char *what);
+
+// full parameter vector of lane/point `g`: the plan's fixed values or a per-group override,
+// with the free parameters written in from theta (column i)
+__device__ inline void load_params(double (&p)[kMaxParams], const KConst &K, const double *base,
+                                   int64_t base_ld, int64_t g, const double *theta, int64_t ld,
+                                   int64_t i) {
+#pragma unroll
+    for (int q = 0; q < kMaxParams; ++q) {
+        p[q] = base ? base[q * base_ld + g] : K.params[q];
+#pragma unroll
+        for (int j = 0; j < kMaxParams; ++j)
+            if (j < K.n_free && K.free_index[j] == q) p[q] = theta[(int64_t)j * ld + i];
+    }
+}
 
 // launchers (forward.hip, pso.hip)
 hipError_t launch_forward(const afm_plan *plan, const FwdArgs &a, hipStream_t s);
@@ -438,11 +460,11 @@ int32_t polish_prec(const afm_plan *plan);
 size_t polish_total_bytes(const afm_plan *plan, int64_t n, int32_t kc);
 hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
                           const int32_t *target_id, const double *targets, int32_t n_targets,
-                          const int32_t *n_cycles, int32_t steps, int32_t kc, double *J_out,
-                          hipStream_t s);
+                          const int32_t *n_cycles, const double *base, int32_t steps, int32_t kc,
+                          double *J_out, hipStream_t s);
 hipError_t enqueue_topk(const afm_plan *plan, const afm_swarm &sw, int32_t k, int32_t *taken,
                         double *zsel, int32_t *tsel, const int32_t *ncyc, int32_t *nsel,
-                        hipStream_t s);
+                        const double *swarm_base, double *bsel, hipStream_t s);
 hipError_t enqueue_merge(const afm_swarm &sw, int32_t k, const double *zsel, const double *Jsel,
                          hipStream_t s);
 constexpr int32_t kPolishStride = 64;  // checkpoint stride of the polish's gradients

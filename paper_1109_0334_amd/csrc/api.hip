@@ -166,6 +166,8 @@ afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_pl
         return st;
     }
     hipError_t e = hipGetDevice(&plan->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&plan->n_cu, hipDeviceAttributeMultiprocessorCount, plan->device);
     if (e == hipSuccess) e = hipMalloc(&plan->d_drive_f, df.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&plan->d_drive_d, dd.size() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&plan->d_lock, lk.size() * sizeof(double));
@@ -338,9 +340,9 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     return AFM_OK;  // the last candidate's results are in the outputs
 }
 
-afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cycles,
-                      const int32_t *target_id, const double *targets, int32_t n_targets,
-                      int32_t steps, double *J, afm_stream_t stream) {
+afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params,
+                      const int32_t *n_cycles, const int32_t *target_id, const double *targets,
+                      int32_t n_targets, int32_t steps, double *J, afm_stream_t stream) {
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     if (n < 0 || steps < 0) return fail(AFM_ERR_INVALID, "n and steps must be >= 0");
     if (plan->prob.n_free < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
@@ -357,7 +359,7 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const int32_t *n_cyc
         plan->pws_bytes = bytes;
     }
     hipError_t e = enqueue_polish(plan, plan->pws, n, z, target_id, targets, n_targets, n_cycles,
-                                  steps, kPolishStride, J, (hipStream_t)stream);
+                                  params, steps, kPolishStride, J, (hipStream_t)stream);
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_polish launch");
 }
 

@@ -114,23 +114,14 @@ __device__ __forceinline__ LaneOut integrate(
     return o;
 }
 
+// One lane's trajectory i (group grp): parameter load, bounds checks, integration, outputs.
 template <int LAW, int NM, bool MIXED, bool BF>
-__global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
+__device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K, int64_t i,
+                                             int64_t grp, int nc) {
     using R = typename std::conditional<MIXED, float, double>::type;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    // full parameter vector: fixed values with this lane's free parameters written in
     double p[kMaxParams];
-#pragma unroll
-    for (int q = 0; q < kMaxParams; ++q) {
-        p[q] = K.params[q];
-#pragma unroll
-        for (int j = 0; j < kMaxParams; ++j)
-            if (j < K.n_free && K.free_index[j] == q) p[q] = A.theta[(int64_t)j * A.ld + i];
-    }
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
     const Law<LAW, R> law(p, K);
-    const int64_t grp = A.group > 0 ? i / A.group : i;
-    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
     const int64_t W = (int64_t)K.lockin * K.N;
     const double *Urow = nullptr;
     bool bad = nc < K.lockin;
@@ -157,16 +148,61 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
     if (A.status) A.status[i] = o.st;
 }
 
+template <int LAW, int NM, bool MIXED, bool BF>
+__global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    lane_forward<LAW, NM, MIXED, BF>(A, K, i, grp, nc);
+}
+
+// Persistent work queue for batches of groups with uneven period counts (one pixel's swarm is
+// one group).  Each wavefront repeatedly takes the next item -- 64 lanes of one group -- from a
+// queue ordered longest first, until the queue is empty; every wave reaches the exit.  The
+// group's period count is the same for all lanes of an item, so it is moved to a scalar
+// register and the time loops run as uniform scalar loops.
+template <int LAW, int NM, bool MIXED, bool BF>
+__global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KConst K) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(A.head, 1);
+        item = __shfl(item, 0, 64);
+        if (item >= A.n_items) break;
+        const int id = A.items[item];
+        const int64_t grp = id / A.chunks;
+        const int64_t local = (int64_t)(id % A.chunks) * 64 + lane;
+        int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+        nc = __builtin_amdgcn_readfirstlane(nc);
+        if (local < A.group) lane_forward<LAW, NM, MIXED, BF>(A, K, grp * A.group + local, grp, nc);
+    }
+}
+
+__global__ void k_queue_reset(int32_t *head) {
+    if (threadIdx.x == 0) *head = 0;
+}
+
 // Small batches (fewer waves than SIMDs) are issue-latency bound: one-wave blocks spread over
 // the CUs and the branch-free law minimises issue slots.  Large batches are throughput bound:
 // 4-wave blocks and the branching law (fewer transcendental ops).
 constexpr int64_t kSmallBatch = 65536;
 
 template <int LAW, int NM, bool MIXED>
-hipError_t launch_t(const FwdArgs &a, const KConst &K, hipStream_t s) {
+hipError_t launch_t(const FwdArgs &a, const KConst &K, int32_t n_cu, hipStream_t s) {
+    constexpr bool branchy = Law<LAW, float>::kBranch;
+    if (a.items) {
+        // persistent grid: 4 waves per SIMD on every CU; the branching law (many waves share
+        // each SIMD)
+        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
+        const unsigned blocks = (unsigned)(n_cu > 0 ? n_cu : 256) * 4;
+        hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, !branchy>), dim3(blocks), dim3(256),
+                           0, s, a, K);
+        return hipGetLastError();
+    }
     const int block = a.n < kSmallBatch ? 64 : 256;
     const int64_t grid = (a.n + block - 1) / block;
-    if constexpr (Law<LAW, float>::kBranch) {
+    if constexpr (branchy) {
         if (a.n >= kSmallBatch) {
             hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, false>), dim3((unsigned)grid),
                                dim3(block), 0, s, a, K);
@@ -179,25 +215,25 @@ hipError_t launch_t(const FwdArgs &a, const KConst &K, hipStream_t s) {
 }
 
 template <int LAW, bool MIXED>
-hipError_t launch_modes(const FwdArgs &a, const KConst &K, hipStream_t s) {
+hipError_t launch_modes(const FwdArgs &a, const KConst &K, int32_t cu, hipStream_t s) {
     switch (K.nm) {
-    case 1: return launch_t<LAW, 1, MIXED>(a, K, s);
-    case 2: return launch_t<LAW, 2, MIXED>(a, K, s);
-    case 3: return launch_t<LAW, 3, MIXED>(a, K, s);
-    case 4: return launch_t<LAW, 4, MIXED>(a, K, s);
+    case 1: return launch_t<LAW, 1, MIXED>(a, K, cu, s);
+    case 2: return launch_t<LAW, 2, MIXED>(a, K, cu, s);
+    case 3: return launch_t<LAW, 3, MIXED>(a, K, cu, s);
+    case 4: return launch_t<LAW, 4, MIXED>(a, K, cu, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <bool MIXED>
-hipError_t launch_law(const FwdArgs &a, const KConst &K, hipStream_t s) {
+hipError_t launch_law(const FwdArgs &a, const KConst &K, int32_t cu, hipStream_t s) {
     switch (K.law) {
-    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(a, K, s);
-    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(a, K, s);
-    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(a, K, s);
-    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(a, K, s);
-    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(a, K, s);
-    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(a, K, s);
+    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(a, K, cu, s);
+    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(a, K, cu, s);
+    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(a, K, cu, s);
+    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(a, K, cu, s);
+    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(a, K, cu, s);
+    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(a, K, cu, s);
     }
     return hipErrorInvalidValue;
 }
@@ -206,8 +242,8 @@ hipError_t launch_law(const FwdArgs &a, const KConst &K, hipStream_t s) {
 
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    if (prec == AFM_PREC_MIXED) return launch_law<true>(a, plan->kc, s);
-    return launch_law<false>(a, plan->kc, s);
+    if (prec == AFM_PREC_MIXED) return launch_law<true>(a, plan->kc, plan->n_cu, s);
+    return launch_law<false>(a, plan->kc, plan->n_cu, s);
 }
 
 hipError_t launch_forward(const afm_plan *plan, const FwdArgs &a, hipStream_t s) {

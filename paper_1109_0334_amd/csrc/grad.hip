@@ -142,17 +142,11 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     constexpr int NB = 2 * NM + 1;  // segment-buffer scalars: x, v, dJ/du of the next state
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
     double p[kMaxParams];
-#pragma unroll
-    for (int q = 0; q < kMaxParams; ++q) {
-        p[q] = K.params[q];
-#pragma unroll
-        for (int j = 0; j < kMaxParams; ++j)
-            if (j < K.n_free && K.free_index[j] == q) p[q] = A.theta[(int64_t)j * A.ld + i];
-    }
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
     const L law(p, K);
     const double zc = p[0] * 1e9;
-    const int64_t grp = A.group > 0 ? i / A.group : i;
     const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
     const int N = K.N;
     const int64_t W = (int64_t)K.lockin * N;

@@ -5,6 +5,10 @@
 // swarm update, then the gather of the best positions -- is captured once on the plan's private
 // stream and replayed with a single graph launch.  Generation numbers are baked into the
 // captured kernel arguments, so a replay needs no host round-trip at all.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
 #include "afm_internal.hpp"
 
 namespace afm {
@@ -17,6 +21,7 @@ struct GraphCache {
     double cutoff = 0;
     const double *targets = nullptr;
     const int32_t *ncyc = nullptr;
+    const double *sparams = nullptr;
     double *best_theta = nullptr, *best_J = nullptr;
     int32_t *gen = nullptr;
     void *ws = nullptr;
@@ -35,7 +40,8 @@ namespace {
 struct WsLayout {
     size_t bytes;
     size_t z, v, pbest_z, theta, pbest_J, J, gbest_z, gbest_J, gen, status;
-    size_t taken, zsel, tsel, nsel, Jsel, polish;  // polish of the top-k (if requested)
+    size_t taken, zsel, tsel, nsel, Jsel, bsel, polish;  // polish of the top-k (if requested)
+    size_t items, head;                                  // persistent queue (uneven periods)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -59,6 +65,8 @@ WsLayout layout(const afm_plan *plan, int32_t D, int32_t S, int32_t P, int32_t k
     L.gbest_J = take(sizeof(double) * S);
     L.gen = take(sizeof(int32_t) * S);
     L.status = take(sizeof(int32_t) * n);
+    L.items = take(sizeof(int32_t) * (size_t)S * ((P + 63) / 64));
+    L.head = take(sizeof(int32_t));
     if (k > 0) {
         const size_t m = (size_t)S * k;
         L.taken = take(sizeof(int32_t) * n);
@@ -66,6 +74,7 @@ WsLayout layout(const afm_plan *plan, int32_t D, int32_t S, int32_t P, int32_t k
         L.tsel = take(sizeof(int32_t) * m);
         L.nsel = take(sizeof(int32_t) * m);
         L.Jsel = take(sizeof(double) * m);
+        L.bsel = take(sizeof(double) * kMaxParams * m);
         L.polish = take(polish_total_bytes(plan, (int64_t)m, kPolishStride));
     }
     L.bytes = off;
@@ -93,7 +102,8 @@ afm_status ensure_workspace(afm_plan *plan, size_t bytes) {
 using namespace afm;
 
 extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
-                                 const int32_t *n_cycles, int32_t particles, int32_t iters,
+                                 const int32_t *n_cycles, const double *swarm_params,
+                                 int32_t particles, int32_t iters,
                                  uint64_t seed, double cutoff, int32_t lbfgs_steps,
                                  int32_t lbfgs_topk, double *best_theta, double *best_J,
                                  int32_t *gen_to_cutoff, afm_stream_t stream) {
@@ -131,8 +141,23 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     const bool hit = g && g->S == n_swarms && g->P == particles && g->T == iters && g->seed == seed &&
                      g->cutoff == cutoff && g->targets == targets && g->ncyc == n_cycles &&
                      g->best_theta == best_theta && g->best_J == best_J && g->gen == gen_to_cutoff &&
-                     g->ws == plan->ws && g->lb_steps == lbfgs_steps && g->lb_k == kpol;
+                     g->ws == plan->ws && g->lb_steps == lbfgs_steps && g->lb_k == kpol &&
+                     g->sparams == swarm_params;
     hipError_t e;
+    const int32_t chunks = (particles + 63) / 64;
+    const int32_t n_items = n_swarms * chunks;
+    if (!hit && n_cycles) {
+        // work queue: the groups' 64-lane chunks, longest period count first (read once, when
+        // the graph is built; the order only affects load balance, never the results)
+        std::vector<int32_t> nc(n_swarms), items(n_items);
+        e = hipMemcpy(nc.data(), n_cycles, sizeof(int32_t) * n_swarms, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "afm_invert reading n_cycles");
+        std::iota(items.begin(), items.end(), 0);
+        std::stable_sort(items.begin(), items.end(),
+                         [&](int32_t a, int32_t b) { return nc[a / chunks] > nc[b / chunks]; });
+        e = hipMemcpy(ws + L.items, items.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "afm_invert queue upload");
+    }
     if (!hit) {
         release_graph(plan);
         g = new GraphCache();
@@ -149,6 +174,14 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         a.n_targets = n_swarms;
         a.group = particles;
         a.row_by_group = 1;
+        a.base = swarm_params;
+        a.base_ld = n_swarms;
+        if (n_cycles) {
+            a.items = (const int32_t *)(ws + L.items);
+            a.n_items = n_items;
+            a.chunks = chunks;
+            a.head = (int32_t *)(ws + L.head);
+        }
         a.J = J;
         a.status = status;
         for (int32_t t = 0; t < iters && e == hipSuccess; ++t) {
@@ -159,13 +192,14 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         if (e == hipSuccess && kpol > 0) {
             const int64_t m = (int64_t)n_swarms * kpol;
             double *zsel = (double *)(ws + L.zsel), *Jsel = (double *)(ws + L.Jsel);
+            double *bsel = (double *)(ws + L.bsel);
             int32_t *tsel = (int32_t *)(ws + L.tsel), *nsel = (int32_t *)(ws + L.nsel);
             e = enqueue_topk(plan, sw, kpol, (int32_t *)(ws + L.taken), zsel, tsel, n_cycles, nsel,
-                             plan->stream);
+                             swarm_params, bsel, plan->stream);
             if (e == hipSuccess)
                 e = enqueue_polish(plan, ws + L.polish, m, zsel, tsel, targets, n_swarms,
-                                   n_cycles ? nsel : nullptr, lbfgs_steps, kPolishStride, Jsel,
-                                   plan->stream);
+                                   n_cycles ? nsel : nullptr, swarm_params ? bsel : nullptr,
+                                   lbfgs_steps, kPolishStride, Jsel, plan->stream);
             if (e == hipSuccess) e = enqueue_merge(sw, kpol, zsel, Jsel, plan->stream);
         }
         if (e == hipSuccess) e = launch_gather_best(plan, sw, best_theta, best_J, gen_to_cutoff, plan->stream);
@@ -195,6 +229,7 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         g->ws = plan->ws;
         g->lb_steps = lbfgs_steps;
         g->lb_k = kpol;
+        g->sparams = swarm_params;
     }
     // order the replay after the caller's earlier work and the caller's later work after it
     e = hipEventRecord(plan->ev_in, (hipStream_t)stream);

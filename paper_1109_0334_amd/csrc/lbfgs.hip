@@ -218,7 +218,8 @@ __global__ void k_copy(int64_t n, const double *src, double *dst) {
 __global__ void __launch_bounds__(256) k_topk(int32_t D, int32_t P, int32_t S, int32_t k,
                                               const double *pbest_J, const double *pbest_z,
                                               int32_t *taken, double *zsel, int32_t *tsel,
-                                              const int32_t *ncyc, int32_t *nsel) {
+                                              const int32_t *ncyc, int32_t *nsel,
+                                              const double *sbase, double *bsel) {
     const int32_t s = blockIdx.x;
     const int64_t n = (int64_t)S * P, base = (int64_t)s * P, m = (int64_t)S * k;
     for (int32_t p = threadIdx.x; p < P; p += blockDim.x) taken[base + p] = 0;
@@ -269,6 +270,8 @@ __global__ void __launch_bounds__(256) k_topk(int32_t D, int32_t P, int32_t S, i
             tsel[(int64_t)s * k + r] = s;
             if (ncyc) nsel[(int64_t)s * k + r] = ncyc[s];
         }
+        if (sbase && threadIdx.x < kMaxParams)
+            bsel[(int64_t)threadIdx.x * m + (int64_t)s * k + r] = sbase[(int64_t)threadIdx.x * S + s];
         __syncthreads();
     }
 }
@@ -353,8 +356,8 @@ static PolishWs carve(void *base, int64_t n, int32_t D, int32_t L) {
 // Enqueue `steps` L-BFGS iterations on n points z [D][n] (in/out) with the given targets.
 hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
                           const int32_t *target_id, const double *targets, int32_t n_targets,
-                          const int32_t *n_cycles, int32_t steps, int32_t kc, double *J_out,
-                          hipStream_t s) {
+                          const int32_t *n_cycles, const double *base, int32_t steps, int32_t kc,
+                          double *J_out, hipStream_t s) {
     const int32_t D = plan->prob.n_free, L = 21;
     const int32_t prec = polish_prec(plan);
     PolishWs w = carve(ws, n, D, L);
@@ -373,6 +376,8 @@ hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
     ga.dJ = w.g;
     ga.status = w.st;
     ga.kc = kc;
+    ga.base = base;
+    ga.base_ld = n;
     ga.seg = (float *)((char *)ws + align256(polish_ws_bytes(n, D, L)));
     ga.ckpt = (float *)((char *)ga.seg + align256(grad_seg_bytes(plan, prec, n, kc)));
     hipError_t e = launch_grad_p(plan, prec, ga, s);
@@ -388,6 +393,8 @@ hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
     fa.targets = targets;
     fa.n_targets = n_targets;
     fa.group = L;
+    fa.base = base;
+    fa.base_ld = n;
     fa.J = w.Jt;
     fa.status = w.stt;
     for (int32_t it = 0; it < steps; ++it) {
@@ -424,10 +431,10 @@ hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
 
 hipError_t enqueue_topk(const afm_plan *plan, const afm_swarm &sw, int32_t k, int32_t *taken,
                         double *zsel, int32_t *tsel, const int32_t *ncyc, int32_t *nsel,
-                        hipStream_t s) {
+                        const double *swarm_base, double *bsel, hipStream_t s) {
     hipLaunchKernelGGL(k_topk, dim3((unsigned)sw.swarms), dim3(256), 0, s, sw.n_dim, sw.particles,
                        sw.swarms, k, (const double *)sw.pbest_J, (const double *)sw.pbest_z, taken,
-                       zsel, tsel, ncyc, nsel);
+                       zsel, tsel, ncyc, nsel, swarm_base, bsel);
     return hipGetLastError();
 }
 

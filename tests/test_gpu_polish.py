@@ -28,10 +28,12 @@ def _truth_z(free, theta):
 
 @pytest.mark.parametrize("polish", ["fp64", "mixed"])
 def test_polish_recovers_truth_like_the_oracle(afm, orc, polish):
-    """Noiseless target, points started 0.01-0.03 (normalised) from the truth, 25 steps.  The
-    FP64 adjoint polish lands where the FP64 oracle's L-BFGS lands; the mixed polish (FP32
-    gradients, best effort where the landscape is corrugated) gets most points to an oracle
-    misfit below 1e-8 and never raises J."""
+    """Noiseless target, points started 0.01-0.03 (normalised) from the truth.  FP64 polish:
+    after 3 steps every point equals the FP64 oracle's L-BFGS iterate (same directions, same
+    accepted Armijo steps); after 25 steps, deep in the flat valley where a 1e-11 gradient
+    difference can flip a borderline Armijo test, it is as close to the truth and as low in J as
+    the oracle's.  Mixed polish (FP32 gradients, best effort where the landscape is corrugated):
+    most points reach an oracle misfit below 1e-8 and J never rises."""
     import torch
 
     c = W.config("c2")
@@ -48,6 +50,13 @@ def test_polish_recovers_truth_like_the_oracle(afm, orc, polish):
     z = torch.tensor(z0, device="cuda")
     J0, _ = plan.misfit(np.stack([[orc.z_to_theta(z0[j, i], *free[j][1:]) for i in range(n)]
                                   for j in range(3)]), U[None, :])
+    if polish == "fp64":
+        z3 = torch.tensor(z0, device="cuda")
+        plan.polish(z3, U[None, :], steps=3)
+        z3 = z3.cpu().numpy()
+        for i in range(n):
+            zo3, _ = orc.lbfgs(m, p_true, free, U, z0[:, i], 3)
+            assert np.max(np.abs(zo3 - z3[:, i])) < 1e-7, (i, zo3, z3[:, i])
     J = plan.polish(z, U[None, :], steps=25).cpu().numpy()
     z = z.cpu().numpy()
     good = 0
@@ -58,11 +67,13 @@ def test_polish_recovers_truth_like_the_oracle(afm, orc, polish):
         Jo_here = orc.forward(m, p, U)["J"]
         zo, Jo = orc.lbfgs(m, p_true, free, U, z0[:, i], 25)
         assert Jo < 1e-9
+        dt_g, dt_o = np.max(np.abs(z[:, i] - zt)), np.max(np.abs(zo - zt))
         print(f"{polish} point {i}: gpu J {J[i]:.3e} (oracle at that point {Jo_here:.3e}), "
-              f"oracle L-BFGS J {Jo:.3e}, |dz| {np.max(np.abs(zo - z[:, i])):.1e}")
+              f"oracle L-BFGS J {Jo:.3e}, |dz| {np.max(np.abs(zo - z[:, i])):.1e}, "
+              f"to truth gpu {dt_g:.1e} oracle {dt_o:.1e}")
         if polish == "fp64":
             assert abs(J[i] - Jo_here) <= 1e-6 * Jo_here + 1e-18
-            assert J[i] <= max(10 * Jo, 1e-12) and np.max(np.abs(zo - z[:, i])) < 1e-4
+            assert J[i] <= max(10 * Jo, 1e-12) and dt_g <= 3 * dt_o + 1e-4
         else:
             assert J[i] <= J0[i].item()
             good += Jo_here < 1e-8

@@ -130,3 +130,45 @@ def test_invert_c2_small_recovers_truth(afm, orc):
     assert abs(Jg - Jo) <= PT.misfit_tol(Jo)
     assert Jo < 1e-4
     assert abs(bt[1] / c["truth"]["Estar"] - 1) < 0.05
+
+
+def test_invert_uneven_queue_matches_oracle(afm, orc):
+    """Several pixels with their own period counts, separations and stiffnesses (the persistent
+    work-queue path, a ragged 70-particle swarm = 2 queue items per pixel), FP64 forward: every
+    swarm follows the oracle swarm step for step."""
+    import torch
+
+    c = W.config("c1")
+    m = dict(c["model"], steps_per_cycle=64, n_cycles=40, lockin_cycles=5)
+    free = W.free_index(c)
+    S, P, T, seed = 3, 70, 5, 11
+    cyc = np.array([40, 25, 33], np.int32)
+    zcs = [14.6e-9, 15.0e-9, 14.2e-9]
+    estar = [1.0e9, 2.5e9, 0.6e9]
+    base = W.full_params(c)
+    sp = np.zeros((8, S))
+    for s in range(S):
+        sp[:5, s] = base
+        sp[0, s], sp[2, s] = zcs[s], estar[s]
+    U = np.stack([orc.forward(dict(m, n_cycles=int(cyc[s])), sp[:5, s], want_trace=True)["trace"]
+                  for s in range(S)])
+    plan = afm.Plan(m, base, free, precision="fp64")
+    out = plan.invert(U, P, T, seed=seed, cutoff=1e-2, n_cycles=cyc, swarm_params=sp)
+    bt, bJ = out["best_theta"].cpu().numpy(), out["best_J"].cpu().numpy()
+    gen = out["gen_to_cutoff"].cpu().numpy()
+    sw = orc.Swarm(len(free), P, S, seed)
+    for t in range(T):
+        J = np.empty(S * P)
+        for s in range(S):
+            ms = dict(m, n_cycles=int(cyc[s]))
+            for p in range(P):
+                q = sp[:5, s].copy()
+                for j, f in enumerate(free):
+                    q[f[0]] = orc.z_to_theta(sw.z[j, s * P + p], *f[1:])
+                J[s * P + p] = orc.forward(ms, q, U[s])["J"]
+        sw.update(J, t, t == T - 1, cutoff=1e-2)
+    for s in range(S):
+        zt = [orc.z_to_theta(sw.gbest_z[j, s], *free[j][1:]) for j in range(len(free))]
+        np.testing.assert_allclose(bt[:, s], zt, rtol=1e-12)
+        assert abs(bJ[s] - sw.gbest_J[s]) <= 1e-9 * sw.gbest_J[s] + 1e-15
+        assert gen[s] == sw.gen_to_cutoff[s]
