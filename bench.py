@@ -36,6 +36,31 @@ PEAK_FP32_SCALAR_ISSUE = 78.6e12
 # out-of-contact force path: 4 stages x (gap 1 + force 4 + acceleration 4) + 3 stage states x 4
 # + slope sums 10 + compensated update 10.
 FLOPS_PER_STEP_DMT1 = 68
+# HBM bytes per launch of that kernel from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by a
+# copy kernel of known size), valid only while the kernel sources are unchanged.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forward_dmt1_c2_pmc.md")
+KERNEL_SOURCES = ["forward.hip", "rk4.hpp", "afm_internal.hpp"]
+
+
+def counted_traffic():
+    """Counter-measured bytes per launch of the benchmark kernel, or None when the summary is
+    missing or the kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    t = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
+    h = re.search(r"^source_sha256:\s*([0-9a-f]{64})", text, re.M)
+    if not (t and h):
+        return None
+    sha = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1109_0334_amd", "csrc", f), "rb") as fh:
+            sha.update(fh.read())
+    return int(t.group(1)) if sha.hexdigest() == h.group(1) else None
 
 
 def parse():
@@ -209,7 +234,8 @@ def main():
     flops = FLOPS_PER_STEP_DMT1 * P * steps_per_traj
     achieved = flops / (k_ms * 1e-3)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_PUBLISHED / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": counted_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
             "kernel": "k_forward<DMT,1 mode,mixed>", "kernel_ms": k_ms,
             "flops_per_launch": flops, "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_ISSUE,
             "occupancy": f"{P} trajectories = {P // 64} waves on 1024 SIMDs"}
