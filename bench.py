@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-pixels", action="store_true", help="skip the uneven pixel-batch leg")
     ap.add_argument("--pixel-steps", type=int, default=2)
+    ap.add_argument("--no-more", action="store_true",
+                    help="skip the time-to-inversion, gradient and 3-mode legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -137,6 +139,111 @@ def pixel_leg(afm, W, dev, steps):
             "plain_grid_forward_ms": grid_ms, "setup_separation_s": t_sep,
             "pixels_without_setpoint_crossing": int((~good).sum()),
             "median_best_J": float(np.median(out["best_J"].cpu().numpy()))}
+
+
+def _event_ms(fn, reps=1):
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def time_to_inversion(afm, W, dev, U, cfg, cutoff):
+    """Whole c2 inversions (all generations) with the mixed and the plain FP64 forward: wall
+    time until sqrt(best J) first reaches the cut-off, and the best J at the end."""
+    import torch
+
+    m, P, T = cfg["model"], cfg["particles"], cfg["iters"]
+    res = {"cutoff_sqrtJ": cutoff, "generations": T}
+    for prec in ("mixed", "fp64"):
+        plan = afm.Plan(m, W.full_params(cfg), W.free_index(cfg), precision=prec, device=dev)
+        plan.invert(U, P, 2, seed=cfg["seed"], cutoff=cutoff)  # workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.invert(U, P, T, seed=cfg["seed"], cutoff=cutoff)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gen = int(out["gen_to_cutoff"].item())
+        res[prec] = {"seconds_all_generations": dt,
+                     "generation_reaching_cutoff": gen,
+                     "seconds_to_cutoff": dt / T * (gen + 1) if gen >= 0 else None,
+                     "final_best_J": float(out["best_J"].item())}
+    if res["mixed"]["seconds_to_cutoff"] and res["fp64"]["seconds_to_cutoff"]:
+        res["fp64_over_mixed"] = res["fp64"]["seconds_to_cutoff"] / res["mixed"]["seconds_to_cutoff"]
+    return res
+
+
+def gradient_leg(afm, W, dev):
+    """c4: discrete-adjoint gradients of 2048 Lennard-Jones-type points, 1000 periods x 256
+    steps, at each checkpoint stride."""
+    import torch
+
+    cfg = W.config("c4")
+    m, free, base = cfg["model"], W.free_index(cfg), W.full_params(cfg)
+    n = int(cfg["points"])
+    ref = afm.Plan(m, base, free, precision="fp64", device=dev)
+    U = ref.forward_batch(torch.tensor([[base[f[0]]] for f in free], device=dev),
+                          trace=True)["trace"].contiguous()
+    th = torch.tensor(W.draw_free(cfg, n, 7).T.copy(), device=dev)
+    plan = afm.Plan(m, base, free, precision="mixed", device=dev)
+    steps = n * m["n_cycles"] * m["steps_per_cycle"]
+    out = {"workload": "c4: 2048 LJ-type points (eps, r0, n, m), 1000 periods x 256 steps",
+           "points": n}
+    fwd_ms = _event_ms(lambda: plan.misfit(th, U))
+    out["forward_misfit_ms"] = fwd_ms
+    for kc in cfg["ckpt_strides"]:
+        plan.grad_batch(th, U, ckpt_stride=kc)
+        ms = _event_ms(lambda: plan.grad_batch(th, U, ckpt_stride=kc))
+        out[f"stride_{kc}"] = {"ms": ms, "gradients_per_s": n / (ms * 1e-3),
+                               "over_forward": ms / fwd_ms}
+    plan.grad_batch(th, U)  # autotuned stride
+    ms = _event_ms(lambda: plan.grad_batch(th, U))
+    out["autotuned"] = {"ms": ms, "gradients_per_s": n / (ms * 1e-3),
+                        "forward_rk4_steps_per_s": steps / (ms * 1e-3)}
+    return out
+
+
+def three_mode_leg(afm, W, dev, gens):
+    """c5: 3-mode Kelvin-Voigt cantilever, 16384 particles, 2000 periods x 512 steps: time per
+    generation, and one L-BFGS step on the best 64 points."""
+    import torch
+
+    cfg = W.config("c5")
+    m, free, base = cfg["model"], W.free_index(cfg), W.full_params(cfg)
+    P = int(cfg["particles"])
+    ref = afm.Plan(m, base, free, precision="fp64", device=dev)
+    U = ref.forward_batch(torch.tensor([[base[f[0]]] for f in free], device=dev),
+                          trace=True)["trace"].contiguous()
+    plan = afm.Plan(m, base, free, precision="mixed", device=dev)
+    plan.invert(U, P, 1, seed=0, cutoff=1e-3)
+    torch.cuda.synchronize()
+    plan.invert(U, P, gens, seed=0, cutoff=1e-3)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.invert(U, P, gens, seed=0, cutoff=1e-3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / gens
+    steps = P * m["n_cycles"] * m["steps_per_cycle"]
+    k = int(cfg["lbfgs_topk"])
+    z = torch.rand(len(free), k, dtype=torch.float64, device=dev, generator=torch.Generator(
+        device=dev).manual_seed(3))
+    plan.polish(z.clone(), U, steps=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.polish(z.clone(), U, steps=1)
+    torch.cuda.synchronize()
+    pol = time.perf_counter() - t0
+    return {"workload": "c5: 3-mode KV + vdW, 5 parameters, 16384 particles, 2000 periods x "
+                        "512 steps, mixed",
+            "ms_per_generation": dt * 1e3, "rk4_steps_per_s": steps / dt,
+            "projected_s_per_inversion_300_generations": dt * cfg["iters"],
+            "lbfgs_step_top64_ms": pol * 1e3,
+            "projected_s_lbfgs_10_steps": pol * cfg["lbfgs_steps"]}
 
 
 def cpu_baseline(cfg, seconds):
@@ -293,6 +400,10 @@ def main():
     line.update(extras)
     if not args.no_pixels:
         line["uneven_pixels"] = pixel_leg(afm, W, dev, max(1, args.pixel_steps))
+    if not args.no_more:
+        line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg, cutoff=0.005)
+        line["gradients"] = gradient_leg(afm, W, dev)
+        line["three_mode"] = three_mode_leg(afm, W, dev, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(line), flush=True)

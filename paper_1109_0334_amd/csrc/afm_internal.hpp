@@ -78,46 +78,94 @@ template <> struct Ops<double> {
 constexpr double kSqrtNano = 3.1622776601683794e-05;
 
 // ------------------------------------------------------------------------------------------
-// Force laws.  Each holds its per-trajectory constants in R; add<BF>(d, dd, b) returns
+// Force laws.  Each holds its per-trajectory constants in R; add<FM>(d, dd, b) returns
 // b + G F / (k 1 nm) for gap d (nm) and gap rate dd (nm per unit tau), written so that the
-// addition folds into the law's last multiply.  BF selects the branch-free form of laws with a
-// contact branch (both pieces evaluated with clamped arguments, no divergent control flow: fewest
-// issue slots when one wave owns a SIMD) or the branching form (each lane evaluates only its own
-// piece: fewer transcendental ops when many waves share a SIMD).
+// addition folds into the law's last multiply.  FM selects how a law with a contact branch is
+// evaluated:
+//   kFmBranch  per-lane branch, each lane evaluates only its own piece (fewest transcendental
+//              ops; the divergent control flow costs scalar instructions, which other waves
+//              hide when many share a SIMD)
+//   kFmFree    branch-free, both pieces with clamped arguments (no control flow)
+//   kFmSkip    the far-field piece always, the contact piece only when some lane of the wave
+//              is in contact, behind one wave-uniform branch (fewest issue slots when one wave
+//              owns a SIMD and contact is rare); laws without this form treat it as kFmFree
+constexpr int kFmBranch = 0;
+constexpr int kFmFree = 1;
+constexpr int kFmSkip = 2;
 
 template <int LAW, typename R> struct Law;
 
 // DMT: out of contact BH / d^2 with BH = -G H R / (6 k) (nm^3); in contact the attraction is
 // frozen at its d = a0 value and BE (a0 - d)^{3/2} is added, BE = G (4/3) E* sqrt(R) 10^-4.5 / k.
 // Branch-free: BH / max(d, a0)^2 + BE max(a0 - d, 0)^{3/2} is the same function.
+//
+// FP32 form of the Hertz term: with ce = sgn(BE) |BE|^{2/3} and q = ce (a0 - d) clamped to the
+// side of zero that ce's sign allows (a median against 0 and +-inf), BE max(a0 - d, 0)^{3/2} =
+// q sqrt(|q|).  That is one fma and one median where the plain form needs a subtraction, a
+// maximum and a multiplication (the sign handling keeps E* < 0 exact, as the oracle computes it).
 template <typename R> struct Law<AFM_LAW_DMT, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = true;
-    R zc, a0, BH, BHa, BE;
+    R zc, a0, BH, BHa, BE, ce, cea0, clim;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
         const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        const double be = K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k;
         zc = (R)(p[0] * 1e9);
         a0 = (R)a0n;
         BH = (R)bh;
         BHa = (R)(bh / (a0n * a0n));
-        BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
+        BE = (R)be;
+        const double c = be < 0.0 ? -::cbrt(be * be) : ::cbrt(be * be);
+        ce = (R)c;
+        cea0 = (R)(c * a0n);
+        clim = be < 0.0 ? -(R)INFINITY : (R)INFINITY;
     }
-    template <bool BF> __device__ inline R add(R d, R, R b) const {
-        if constexpr (BF) {
-            const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
-            const R del = Ops<R>::max(a0 - d, R(0));
-            return Ops<R>::fma(BE * del, Ops<R>::sqrt(del), Ops<R>::fma(BH * r, r, b));
-        } else {
-            R f;
-            if (d > a0) {
-                const R r = Ops<R>::rcp(d);
-                f = Ops<R>::fma(BH * r, r, b);
+    template <int FM> __device__ inline R add(R d, R, R b) const {
+        if constexpr (std::is_same<R, float>::value) {
+            if constexpr (FM != kFmBranch) {
+                // max(d, a0) as a median against the largest finite float (equal for every
+                // finite d): IEEE-mode v_max would first quiet both operands, two extra
+                // instructions per pass of the time loop
+                const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
+                R f = Ops<R>::fma(BH * r, r, b);
+                // the Hertz term is zero unless d < a0 (up to the rounding of ce a0, which
+                // gives at most a term of (1 ulp of ce a0)^{3/2} at d = a0)
+                if (FM == kFmFree || __builtin_amdgcn_ballot_w64(d < a0) != 0) {
+                    // a scheduling barrier (no instruction, no memory effect) keeps the compiler
+                    // from speculating this block into a select evaluated on every pass
+                    if constexpr (FM == kFmSkip) __builtin_amdgcn_sched_barrier(0);
+                    const R q = __builtin_amdgcn_fmed3f(Ops<R>::fma(-ce, d, cea0), R(0), clim);
+                    f = Ops<R>::fma(q, Ops<R>::sqrt(__builtin_fabsf(q)), f);
+                }
+                return f;
             } else {
-                const R del = a0 - d;
-                f = Ops<R>::fma(BE * del, Ops<R>::sqrt(del), b + BHa);
+                R f;
+                if (d > a0) {
+                    const R r = Ops<R>::rcp(d);
+                    f = Ops<R>::fma(BH * r, r, b);
+                } else {
+                    const R q = Ops<R>::fma(-ce, d, cea0);
+                    f = Ops<R>::fma(q, Ops<R>::sqrt(__builtin_fabsf(q)), b + BHa);
+                }
+                return f;
             }
-            return f;
+        } else {
+            if constexpr (FM != kFmBranch) {
+                const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+                const R del = Ops<R>::max(a0 - d, R(0));
+                return Ops<R>::fma(BE * del, Ops<R>::sqrt(del), Ops<R>::fma(BH * r, r, b));
+            } else {
+                R f;
+                if (d > a0) {
+                    const R r = Ops<R>::rcp(d);
+                    f = Ops<R>::fma(BH * r, r, b);
+                } else {
+                    const R del = a0 - d;
+                    f = Ops<R>::fma(BE * del, Ops<R>::sqrt(del), b + BHa);
+                }
+                return f;
+            }
         }
     }
 
@@ -163,7 +211,7 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
         n = (R)p[3];
         m = (R)p[4];
     }
-    template <bool BF> __device__ inline R add(R d, R, R b) const {
+    template <int FM> __device__ inline R add(R d, R, R b) const {
         const R ls = lr0 - Ops<R>::log2(d);
         return Ops<R>::fma(BL * Ops<R>::rcp(d), Ops<R>::exp2(n * ls) - Ops<R>::exp2(m * ls), b);
     }
@@ -212,8 +260,8 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
         BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
         BV = (R)(-K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k);
     }
-    template <bool BF> __device__ inline R add(R d, R dd, R b) const {
-        if constexpr (BF) {
+    template <int FM> __device__ inline R add(R d, R dd, R b) const {
+        if constexpr (FM != kFmBranch) {
             const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
             const R del = Ops<R>::max(a0 - d, R(0));
             return Ops<R>::fma(Ops<R>::sqrt(del), Ops<R>::fma(BE, del, BV * dd),
@@ -274,7 +322,7 @@ template <typename R> struct Law<AFM_LAW_HOOKE, R> {
         zc = (R)(p[0] * 1e9);
         BK = (R)(-K.G * p[1] / K.k);
     }
-    template <bool BF> __device__ inline R add(R d, R, R b) const {
+    template <int FM> __device__ inline R add(R d, R, R b) const {
         return d < R(0) ? Ops<R>::fma(BK, d, b) : b;
     }
 
@@ -303,7 +351,7 @@ template <typename R> struct Law<AFM_LAW_SD, R> {
         BK = (R)(-K.G * p[1] / K.k);
         BS = (R)(-K.G * p[2] * K.wd / K.k);
     }
-    template <bool BF> __device__ inline R add(R d, R dd, R b) const {
+    template <int FM> __device__ inline R add(R d, R dd, R b) const {
         return d < R(0) ? Ops<R>::fma(BK, d, Ops<R>::fma(BS, dd, b)) : b;
     }
 
@@ -329,7 +377,7 @@ template <typename R> struct Law<AFM_LAW_NONE, R> {
     static constexpr bool kBranch = false;
     R zc;
     __device__ Law(const double *p, const KConst &) { zc = (R)(p[0] * 1e9); }
-    template <bool BF> __device__ inline R add(R, R, R b) const { return b; }
+    template <int FM> __device__ inline R add(R, R, R b) const { return b; }
 
     static constexpr int NC = 1;  // no constants; one unused slot keeps array types valid
     __device__ inline R grad(R, R, R &Fd, R &Fdd, R (&dc)[NC]) const {

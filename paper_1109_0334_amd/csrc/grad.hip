@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 cdn = kc;
             }
             --cdn;
-            rk4_step<NM, COMP, true>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
                                      Dt[2 * s + 1], Dt[2 * s + 2]);
             if (n + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                     sgd[(k * NB + NM + m) * n_lanes + i] = v[m];
                 }
             }
-            rk4_step<NM, COMP, true>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
                                      Dt[2 * s + 1], Dt[2 * s + 2]);
             if (q + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);

@@ -13,7 +13,7 @@ namespace afm {
 // uses x_1 = g - z_c, which needs only absolute precision.
 //
 // Slopes of the modal system at state (g, x_2.., v_1..): returns the accelerations a_i.
-template <int NM, bool BF, typename R, class L>
+template <int NM, int FM, typename R, class L>
 __device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&v)[NM],
                                       const R (&om2)[NM], const R (&cd)[NM], const R (&gn)[NM],
                                       R D, R (&a)[NM]) {
@@ -27,11 +27,14 @@ __device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&
         for (int i = 1; i < NM; ++i) dd += v[i];
     }
     if constexpr (NM == 1) {
-        // point mass: the drive table already carries the mode's gain
+        // point mass: the drive table already carries the mode's gain.  The restoring term keeps
+        // its own (g - z_c): folding om2 z_c into the drive values instead would round the small
+        // drive (a = A0/Q) against a z_c-sized sum, the same error every period, which the
+        // resonance then amplifies by Q.
         a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc,
-                           Ops<R>::fma(-cd[0], v[0], law.template add<BF>(d, dd, D)));
+                           Ops<R>::fma(-cd[0], v[0], law.template add<FM>(d, dd, D)));
     } else {
-        const R F = law.template add<BF>(d, dd, R(0));
+        const R F = law.template add<FM>(d, dd, R(0));
         a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc, Ops<R>::fma(-cd[0], v[0], Ops<R>::fma(gn[0], D, F)));
 #pragma unroll
         for (int i = 1; i < NM; ++i)
@@ -41,12 +44,12 @@ __device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&
 
 // One classical RK4 step, c = (0, 1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6).  D0, D1, D2 are the
 // drive terms at t, t + h/2, t + h.  COMP: Kahan-compensated update of the state.
-template <int NM, bool COMP, bool BF, typename R, class L>
+template <int NM, bool COMP, int FM, typename R, class L>
 __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R (&cx)[NM],
                                          R (&cv)[NM], const R (&om2)[NM], const R (&cd)[NM],
                                          const R (&gn)[NM], R h, R h2, R h6, R D0, R D1, R D2) {
     R a[NM], sx[NM], sv[NM], xs[NM], vs[NM];
-    accel<NM, BF>(law, x, v, om2, cd, gn, D0, a);
+    accel<NM, FM>(law, x, v, om2, cd, gn, D0, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         sx[i] = v[i];
@@ -54,7 +57,7 @@ __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R
         xs[i] = Ops<R>::fma(h2, v[i], x[i]);
         vs[i] = Ops<R>::fma(h2, a[i], v[i]);
     }
-    accel<NM, BF>(law, xs, vs, om2, cd, gn, D1, a);
+    accel<NM, FM>(law, xs, vs, om2, cd, gn, D1, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         const R kx = vs[i];
@@ -63,7 +66,7 @@ __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R
         xs[i] = Ops<R>::fma(h2, kx, x[i]);
         vs[i] = Ops<R>::fma(h2, a[i], v[i]);
     }
-    accel<NM, BF>(law, xs, vs, om2, cd, gn, D1, a);
+    accel<NM, FM>(law, xs, vs, om2, cd, gn, D1, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         const R kx = vs[i];
@@ -72,7 +75,7 @@ __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R
         xs[i] = Ops<R>::fma(h, kx, x[i]);
         vs[i] = Ops<R>::fma(h, a[i], v[i]);
     }
-    accel<NM, BF>(law, xs, vs, om2, cd, gn, D2, a);
+    accel<NM, FM>(law, xs, vs, om2, cd, gn, D2, a);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         sx[i] += vs[i];
