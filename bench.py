@@ -80,9 +80,10 @@ def parse():
     return ap.parse_args()
 
 
-def pixel_leg(afm, W, dev, steps):
-    """Uneven batching: 4096 pixel inversions of (H, E*) with per-pixel E*, set-point and period
-    count (100..2000), 128 particles, through the persistent work-queue kernel."""
+def _pixel_problem(afm, W, dev, S):
+    """The first S pixels of the uneven-batching workload: per-pixel separations from their
+    set-points (batched FP64 forward solves), parameters [8][S] and FP64 targets over each
+    pixel's own period count."""
     import numpy as np
     import torch
 
@@ -90,9 +91,7 @@ def pixel_leg(afm, W, dev, steps):
 
     cfg = W.config("c3")
     m = cfg["model"]
-    pix = W.pixels(cfg)
-    S, P = int(cfg["pixels"]), int(cfg["particles"])
-    N, Wn = m["steps_per_cycle"], m["lockin_cycles"] * m["steps_per_cycle"]
+    pix = {k: v[:S] for k, v in W.pixels(cfg).items()}
     base = W.full_params(cfg)
     t0 = time.perf_counter()
     zc = setpoint.separations(afm, m, base, [2], [pix["Estar"]], pix["setpoint"], device=dev)
@@ -102,14 +101,27 @@ def pixel_leg(afm, W, dev, steps):
     sp = np.concatenate([sp, np.zeros((8 - sp.shape[0], S))], axis=0)
     sp[0] = np.where(good, zc, base[0])
     sp[2] = pix["Estar"]
-    # targets: plain FP64 forward at each pixel's truth over its own period count
     ref = afm.Plan(m, base, [(0, 0.0, 1.0, 0), (2, 0.0, 1.0, 0)], precision="fp64", device=dev)
     th = torch.tensor(np.stack([sp[0], sp[2]]), device=dev)
     cyc = torch.tensor(pix["cycles"], device=dev)
     U = ref.forward_batch(th, n_cycles=cyc, trace=True)["trace"].contiguous()
+    return dict(cfg=cfg, m=m, base=base, pix=pix, U=U, cyc=cyc, spd=torch.tensor(sp, device=dev),
+                t_sep=t_sep, good=good)
+
+
+def pixel_leg(afm, W, dev, steps):
+    """Uneven batching: 4096 pixel inversions of (H, E*) with per-pixel E*, set-point and period
+    count (100..2000), 128 particles, through the persistent work-queue kernel."""
+    import numpy as np
+    import torch
+
+    cfg = W.config("c3")
+    S, P = int(cfg["pixels"]), int(cfg["particles"])
+    q = _pixel_problem(afm, W, dev, S)
+    m, U, cyc, spd, pix = q["m"], q["U"], q["cyc"], q["spd"], q["pix"]
+    N = m["steps_per_cycle"]
     free = W.free_index(cfg)
-    plan = afm.Plan(m, base, free, precision="mixed", device=dev)
-    spd = torch.tensor(sp, device=dev)
+    plan = afm.Plan(m, q["base"], free, precision="mixed", device=dev)
     plan.invert(U, P, 1, seed=0, n_cycles=cyc, swarm_params=spd)
     torch.cuda.synchronize()
     plan.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)  # capture
@@ -123,12 +135,7 @@ def pixel_leg(afm, W, dev, steps):
     th_all = torch.tensor(W.draw_free(cfg, S * P, 9).T.copy(), device=dev)
     tid = torch.arange(S, device=dev, dtype=torch.int32).repeat_interleave(P)
     ncl = cyc.repeat_interleave(P)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    plan.misfit(th_all, U, target_id=tid, n_cycles=ncl)
-    e1.record()
-    torch.cuda.synchronize()
-    grid_ms = e0.elapsed_time(e1)
+    grid_ms = _event_ms(lambda: plan.misfit(th_all, U, target_id=tid, n_cycles=ncl))
     sat = FLOPS_PER_STEP_DMT1 * rk4 / dt
     return {"workload": "c3-uneven: 4096 pixels x 128 particles, DMT, invert (H, log E*), "
                         "periods U{100..2000} x 256 steps, per-pixel E* and set-point",
@@ -136,9 +143,41 @@ def pixel_leg(afm, W, dev, steps):
             "rk4_steps_per_s": rk4 / dt, "inversions_per_s": S / (dt / steps * cfg["iters"]),
             "achieved_tflops": sat / 1e12, "frac_published_peak": sat / PEAK_FP32_PUBLISHED,
             "frac_scalar_issue_peak": sat / PEAK_FP32_SCALAR_ISSUE,
-            "plain_grid_forward_ms": grid_ms, "setup_separation_s": t_sep,
-            "pixels_without_setpoint_crossing": int((~good).sum()),
+            "plain_grid_forward_ms": grid_ms, "setup_separation_s": q["t_sep"],
+            "pixels_without_setpoint_crossing": int((~q["good"]).sum()),
             "median_best_J": float(np.median(out["best_J"].cpu().numpy()))}
+
+
+def pixel_time_to_inversion(afm, W, dev, S, cutoff):
+    """Whole inversions (all generations) of the first S pixels, mixed vs plain FP64 forward:
+    wall time, the generation at which each pixel's sqrt(best J) first reaches the cut-off."""
+    import numpy as np
+    import torch
+
+    cfg = W.config("c3")
+    P, T = int(cfg["particles"]), int(cfg["iters"])
+    q = _pixel_problem(afm, W, dev, S)
+    res = {"pixels": S, "generations": T, "cutoff_sqrtJ": cutoff}
+    for prec in ("mixed", "fp64"):
+        plan = afm.Plan(q["m"], q["base"], W.free_index(cfg), precision=prec, device=dev)
+        kw = dict(seed=0, cutoff=cutoff, n_cycles=q["cyc"], swarm_params=q["spd"])
+        plan.invert(q["U"], P, 2, **kw)  # workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.invert(q["U"], P, T, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gen = out["gen_to_cutoff"].cpu().numpy()
+        ok = gen >= 0
+        res[prec] = {"seconds_all_generations": dt, "fraction_reaching_cutoff": float(ok.mean()),
+                     "median_generation_reaching_cutoff": float(np.median(gen[ok])) if ok.any() else None,
+                     "seconds_to_cutoff_median": dt / T * (float(np.median(gen[ok])) + 1)
+                     if ok.any() else None,
+                     "median_final_best_J": float(np.median(out["best_J"].cpu().numpy()))}
+    if res["mixed"]["seconds_to_cutoff_median"] and res["fp64"]["seconds_to_cutoff_median"]:
+        res["fp64_over_mixed"] = (res["fp64"]["seconds_to_cutoff_median"]
+                                  / res["mixed"]["seconds_to_cutoff_median"])
+    return res
 
 
 def _event_ms(fn, reps=1):
@@ -153,15 +192,23 @@ def _event_ms(fn, reps=1):
     return e0.elapsed_time(e1) / reps
 
 
-def time_to_inversion(afm, W, dev, U, cfg, cutoff):
-    """Whole c2 inversions (all generations) with the mixed and the plain FP64 forward: wall
-    time until sqrt(best J) first reaches the cut-off, and the best J at the end."""
+def time_to_inversion(afm, W, dev, U, cfg):
+    """Whole c2 inversions (all generations), mixed vs plain FP64 forward, at equal misfit
+    accuracy.  The noisy target puts a floor under J, so the accuracy is stated relative to it:
+    a first mixed run finds the floor J_f (its final best J); both precisions then run with the
+    cut-off sqrt(J) <= sqrt(1.01 J_f) and report the generation and wall time that reach it."""
+    import math
+
     import torch
 
     m, P, T = cfg["model"], cfg["particles"], cfg["iters"]
-    res = {"cutoff_sqrtJ": cutoff, "generations": T}
-    for prec in ("mixed", "fp64"):
-        plan = afm.Plan(m, W.full_params(cfg), W.free_index(cfg), precision=prec, device=dev)
+    plans = {prec: afm.Plan(m, W.full_params(cfg), W.free_index(cfg), precision=prec, device=dev)
+             for prec in ("mixed", "fp64")}
+    first = plans["mixed"].invert(U, P, T, seed=cfg["seed"], cutoff=0.0)
+    floor = float(first["best_J"].item())
+    cutoff = math.sqrt(1.01 * floor)
+    res = {"generations": T, "J_floor": floor, "cutoff_sqrtJ": cutoff}
+    for prec, plan in plans.items():
         plan.invert(U, P, 2, seed=cfg["seed"], cutoff=cutoff)  # workspace
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -246,17 +293,29 @@ def three_mode_leg(afm, W, dev, gens):
             "projected_s_lbfgs_10_steps": pol * cfg["lbfgs_steps"]}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(cfg, seconds):
-    """Oracle misfit of C2 particles, one host core, until `seconds` of work (max 4000)."""
+    """Oracle misfit of c2 particles on one host core until `seconds` of work (max 4000), plus
+    ns per RK4 step of the oracle for the other force models (a few short trajectories each)."""
     import numpy as np
 
     import oracle
+    import workloads as W
 
     m = cfg["model"]
-    base = __import__("workloads").full_params(cfg)
+    base = W.full_params(cfg)
     U = np.sin(np.arange(m["lockin_cycles"] * m["steps_per_cycle"]) * 0.1) * 1.6e-8
-    th = __import__("workloads").draw_free(cfg, 4000, 99)
-    free = __import__("workloads").free_index(cfg)
+    th = W.draw_free(cfg, 4000, 99)
+    free = W.free_index(cfg)
     steps_per = m["n_cycles"] * m["steps_per_cycle"]
     t0 = time.perf_counter()
     n = 0
@@ -269,9 +328,31 @@ def cpu_baseline(cfg, seconds):
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
+    ns = {"dmt_point_mass": dt / (n * steps_per) * 1e9}
+    for name, key, cycles, reps in (("lj_point_mass", "c4", 40, 4), ("kv_3mode", "c5", 20, 2)):
+        c = W.config(key)
+        mm = dict(c["model"], n_cycles=cycles)
+        pp = W.full_params(c)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            oracle.forward(mm, pp)
+        ns[name] = (time.perf_counter() - t1) / (reps * cycles * mm["steps_per_cycle"]) * 1e9
     return {"value": n * steps_per / dt, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} particles of the workload (misfit, {m['n_cycles']} periods x "
-                      f"{m['steps_per_cycle']} steps each), FP64, single thread, {dt:.1f} s"}
+                      f"{m['steps_per_cycle']} steps each), FP64, single thread, {dt:.1f} s",
+            "ns_per_rk4_step": ns, "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
+
+
+PAPER_CONTEXT = {
+    "note": "the paper's own timings, other hardware and workloads; context, not a target",
+    "gpu": "NVIDIA Quadro FX 5800 (240 cores), FP32",
+    "cpu": "one core of a 2 GHz Xeon",
+    "single_forward_solve_s": {"cpu": 0.482, "gpu": 0.0151},
+    "batched": "960 solves (8 modes, 1000 RK4 steps) in 0.0151 s",
+    "derived_gpu_trajectory_steps_per_s": 6.36e7,
+    "derived_cpu_trajectory_steps_per_s": 2.07e3,
+    "pso_generation_ms": 16,
+}
 
 
 def main():
@@ -401,11 +482,13 @@ def main():
     if not args.no_pixels:
         line["uneven_pixels"] = pixel_leg(afm, W, dev, max(1, args.pixel_steps))
     if not args.no_more:
-        line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg, cutoff=0.005)
+        line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg)
+        line["time_to_inversion_pixels"] = pixel_time_to_inversion(afm, W, dev, 256, cutoff=1e-3)
         line["gradients"] = gradient_leg(afm, W, dev)
         line["three_mode"] = three_mode_leg(afm, W, dev, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
 

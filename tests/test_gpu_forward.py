@@ -252,3 +252,37 @@ def test_saturating_batch_sampled(afm, orc):
     o = PT.oracle_batch(orc, m, P)
     failing, excluded = PT.compare_mixed(orc, m, P, o, A[idx], phi[idx], st[idx], tag="saturating")
     assert not failing and len(excluded) <= 1
+
+
+@pytest.mark.parametrize("N", [4, 5, 203, 4096])
+def test_steps_per_period_edges(afm, orc, N):
+    """Step counts at the validated limits (4 and 4096) and ones the 4-step inner blocks do not
+    divide (5, 203), plain FP64 path, 67 points (a ragged second wave): equal to the oracle to
+    rounding; the status (a step of a quarter period can blow up in contact) equal too."""
+    c = W.config("c1")
+    nc = max(3, 40000 // N)
+    m = dict(c["model"], steps_per_cycle=N, n_cycles=nc, lockin_cycles=2)
+    plan = _plan(afm, c, "fp64", model=m)
+    th = _theta(c, 67, 20 + N)
+    A, phi, st = _np(plan.forward_batch(th))
+    P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
+    o = PT.oracle_batch(orc, m, P)
+    assert np.array_equal(st, o["status"])
+    ok = st == 0
+    np.testing.assert_allclose(A[ok], o["A"][ok], rtol=PT.FP64_RTOL)
+    assert np.max(np.abs(PT.wrap(phi[ok] - o["phi"][ok])), initial=0.0) < PT.FP64_RTOL
+
+
+@pytest.mark.parametrize("N", [203, 4096])
+def test_steps_per_period_edges_mixed(afm, orc, N):
+    """The same step counts on the mixed path (remainder steps after the 4-step blocks)."""
+    c = W.config("c2")
+    nc = max(4, 60000 // N)
+    m = dict(c["model"], steps_per_cycle=N, n_cycles=nc, lockin_cycles=2)
+    plan = _plan(afm, c, "mixed", model=m)
+    th = _theta(c, 40, 30 + N)
+    A, phi, st = _np(plan.forward_batch(th))
+    P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
+    o = PT.oracle_batch(orc, m, P)
+    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, tag=f"N={N}")
+    assert not failing and len(excluded) <= 2

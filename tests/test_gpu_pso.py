@@ -172,3 +172,46 @@ def test_invert_uneven_queue_matches_oracle(afm, orc):
         np.testing.assert_allclose(bt[:, s], zt, rtol=1e-12)
         assert abs(bJ[s] - sw.gbest_J[s]) <= 1e-9 * sw.gbest_J[s] + 1e-15
         assert gen[s] == sw.gen_to_cutoff[s]
+
+
+def test_invert_degenerate_shapes(afm, orc):
+    """One particle, one generation, two swarms (FP64 forward): the best is the initial particle,
+    exactly as the oracle draws it."""
+    c = W.config("c1")
+    m = dict(c["model"], n_cycles=30, lockin_cycles=3)
+    U = orc.forward(m, W.full_params(c), want_trace=True)["trace"]
+    plan = afm.Plan(m, W.full_params(c), W.free_index(c), precision="fp64")
+    out = plan.invert(np.stack([U, 0.9 * U]), 1, 1, seed=5, cutoff=1e-2)
+    sw = orc.Swarm(2, 1, 2, 5)
+    J = np.empty(2)
+    for s, Us in enumerate((U, 0.9 * U)):
+        q = W.full_params(c).copy()
+        for j, f in enumerate(W.free_index(c)):
+            q[f[0]] = orc.z_to_theta(sw.z[j, s], *f[1:])
+        J[s] = orc.forward(m, q, Us)["J"]
+    sw.update(J, 0, True, cutoff=1e-2)
+    bt = out["best_theta"].cpu().numpy()
+    for s in range(2):
+        zt = [orc.z_to_theta(sw.gbest_z[j, s], *W.free_index(c)[j][1:]) for j in range(2)]
+        np.testing.assert_allclose(bt[:, s], zt, rtol=1e-12)
+        assert abs(out["best_J"].cpu().numpy()[s] - sw.gbest_J[s]) <= 1e-9 * sw.gbest_J[s]
+
+
+def test_invert_bad_pixel_does_not_touch_the_others(afm, orc):
+    """A pixel whose period count is shorter than the lock-in window gets status BAD_INPUT for
+    every particle (best J = inf, cut-off never reached); every other pixel's swarm is
+    bit-identical to a run where that pixel was valid (swarms are independent streams)."""
+    c = W.config("c1")
+    m = dict(c["model"], steps_per_cycle=64, n_cycles=40, lockin_cycles=5)
+    free = W.free_index(c)
+    base = W.full_params(c)
+    U = orc.forward(m, base, want_trace=True)["trace"]
+    targets = np.stack([U, U, U])
+    res = []
+    for cyc in ([40, 25, 33], [40, 3, 33]):
+        plan = afm.Plan(m, base, free, precision="mixed")
+        out = plan.invert(targets, 70, 4, seed=9, cutoff=1e-2, n_cycles=np.array(cyc, np.int32))
+        res.append({k: v.cpu().numpy() for k, v in out.items()})
+    for k in res[0]:
+        assert np.array_equal(res[0][k][..., [0, 2]], res[1][k][..., [0, 2]]), k
+    assert np.isinf(res[1]["best_J"][1]) and res[1]["gen_to_cutoff"][1] == -1
