@@ -37,7 +37,8 @@ LAW_PARAMS = {
 IC = {"free_steady": 0, "rest": 1}
 POLISH = {"plan": 0, "mixed": 1, "fp64": 2}
 ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
-EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
+EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
+           "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
            "afm_last_error", "afm_version")
 
@@ -85,6 +86,7 @@ def lib() -> C.CDLL:
     vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     L.afm_plan_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(vp)]
     L.afm_plan_destroy.argtypes = [vp]
+    L.afm_set_launch_shape.argtypes = [vp, i32, i32]
     L.afm_forward_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.afm_misfit.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp]
     L.afm_grad_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
@@ -219,6 +221,11 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_launch_shape(self, block=0, tpl=1):
+        """Pin the plain forward kernel's launch shape (block lanes, trajectories per lane);
+        block=0 returns to autotuning."""
+        _check(lib().afm_set_launch_shape(self._h, int(block), int(tpl)), "afm_set_launch_shape")
 
     def forward_batch(self, theta, n_cycles=None, trace=False):
         """theta [n_free][n] (SI) -> dict(amp [n] m, phase [n] rad, status [n], trace [n][W])."""

@@ -15,7 +15,9 @@
 #include <cmath>
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <type_traits>
+#include <vector>
 
 #include "afm.h"
 
@@ -107,6 +109,7 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = true;
     R zc, a0, BH, BHa, BE, ce, cea0, clim;
+    Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
         const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
@@ -204,6 +207,7 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = false;
     R zc, BL, lr0, n, m;
+    Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
         BL = (R)(K.G * p[1] * p[3] * p[4] / (p[3] - p[4]) / (K.k * 1e-18));
@@ -250,6 +254,7 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
     static constexpr bool kRate = true;
     static constexpr bool kBranch = true;
     R zc, a0, BH, BHa, BE, BV;
+    Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
         const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
@@ -318,6 +323,7 @@ template <typename R> struct Law<AFM_LAW_HOOKE, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = false;
     R zc, BK;
+    Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
         BK = (R)(-K.G * p[1] / K.k);
@@ -346,6 +352,7 @@ template <typename R> struct Law<AFM_LAW_SD, R> {
     static constexpr bool kRate = true;
     static constexpr bool kBranch = false;
     R zc, BK, BS;
+    Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         zc = (R)(p[0] * 1e9);
         BK = (R)(-K.G * p[1] / K.k);
@@ -376,6 +383,7 @@ template <typename R> struct Law<AFM_LAW_NONE, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = false;
     R zc;
+    Law() = default;
     __device__ Law(const double *p, const KConst &) { zc = (R)(p[0] * 1e9); }
     template <int FM> __device__ inline R add(R, R, R b) const { return b; }
 
@@ -438,6 +446,21 @@ struct GraphCache;
 
 }  // namespace afm
 
+namespace afm {
+// Launch shape of a plain forward launch and the plan's record of tuned shapes.
+struct FwdShape {
+    int32_t block;  // lanes per workgroup: 64, 128 or 256
+    int32_t tpl;    // trajectories per lane: 1 or 2
+};
+struct FwdTune {
+    int64_t n;       // batch size
+    int32_t prec;    // AFM_PREC_*
+    int32_t has_nc;  // per-trajectory period counts given
+    FwdShape shape;
+    float ms;        // the winning candidate's time
+};
+}  // namespace afm
+
 struct afm_plan {
     afm_problem prob;
     int32_t precision;
@@ -463,6 +486,9 @@ struct afm_plan {
     size_t pws_bytes = 0;
     // PSO constants
     double pso_w, pso_c1, pso_c2, pso_vmax;
+    // tuned launch shapes of plain forward launches (filled on first use of a batch size)
+    mutable std::vector<afm::FwdTune> fwd_tune;
+    afm::FwdShape pinned_shape{0, 0};  // block 0: tuned
 };
 
 namespace afm {
@@ -500,6 +526,11 @@ hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double 
 hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s);
 hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s);
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
+// tuned (or, under stream capture, default) shape of a plain forward launch; `launch` runs one
+// candidate on the real arguments
+hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, bool pair_ok,
+                         hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
+                         FwdShape *out);
 size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
 size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
 int32_t polish_prec(const afm_plan *plan);

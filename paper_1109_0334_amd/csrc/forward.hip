@@ -23,12 +23,16 @@ struct LaneOut {
     int32_t st;
 };
 
-// Integrate one trajectory of nc periods and reduce it.  zc: separation in nm (FP64).
-// Urow: measured window trace (m) or nullptr; trow: window trace output (m) or nullptr.
-template <int LAW, int NM, bool MIXED, int FM>
-__device__ __forceinline__ LaneOut integrate(
-    const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
-    const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow) {
+// Integrate T trajectories of nc periods each in one lane and reduce them.  zc: separations in
+// nm (FP64).  Urow: measured window traces (m) or nullptr; trow: window trace outputs (m) or
+// nullptr.  With T > 1 the trajectories advance step by step side by side (independent
+// instruction streams the scheduler interleaves) and share the drive-table loads; a trajectory
+// that fails keeps being stepped (its results are discarded) until all have failed.
+template <int LAW, int NM, bool MIXED, int FM, int T>
+__device__ __forceinline__ void integrate(
+    const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
+    const double (&zc)[T], const KConst &K, int nc, const double *const (&Urow)[T],
+    double *const (&trow)[T], LaneOut (&o)[T]) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     const R *__restrict__ Dt;
@@ -37,23 +41,31 @@ __device__ __forceinline__ LaneOut integrate(
     const double *__restrict__ Lc = K.lock_c;
     const double *__restrict__ Ls = K.lock_s;
 
-    R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
+    R x[T][NM], v[T][NM], cx[T][NM], cv[T][NM], om2[NM], cd[NM], gn[NM];
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
-        x[i] = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
-        v[i] = (R)K.y0[NM + i];
-        cx[i] = R(0);
-        cv[i] = R(0);
         om2[i] = (R)K.om2[i];
         cd[i] = (R)K.cdamp[i];
         gn[i] = (R)K.gain[i];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            x[t][i] = (R)(i == 0 ? zc[t] + K.y0[0] : K.y0[i]);
+            v[t][i] = (R)K.y0[NM + i];
+            cx[t][i] = R(0);
+            cv[t][i] = R(0);
+        }
     }
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     const int N = K.N;
     const int c_win = nc - K.lockin;
     const double lim = K.div_nm;
-    double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
-    int32_t st = 0;
+    double Sc[T], Ss[T], Jn[T], Jd[T];
+    int32_t st[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        Sc[t] = Ss[t] = Jn[t] = Jd[t] = 0.0;
+        st[t] = 0;
+    }
 
     for (int c = 0; c < nc; ++c) {
         if (c < c_win) {
@@ -69,108 +81,171 @@ __device__ __forceinline__ LaneOut integrate(
                 CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
                 const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
                         e6 = dp[6], e7 = dp[7], e8 = dp[8];
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e0, e1, e2);
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e2, e3, e4);
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e4, e5, e6);
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e6, e7, e8);
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, e0, e1, e2);
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, e2, e3, e4);
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, e4, e5, e6);
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, e6, e7, e8);
             }
-            for (; s < N; ++s)
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                       Dt[2 * s + 1], Dt[2 * s + 2]);
+            for (; s < N; ++s) {
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
+            }
         } else {
             const int w0 = (c - c_win) * N;
-            const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
-            double Un = Up ? Up[0] : 0.0;
+            const double *__restrict__ Up[T];
+            double Un[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                Up[t] = Urow[t] ? Urow[t] + w0 : nullptr;
+                Un[t] = Up[t] ? Up[t][0] : 0.0;
+            }
             for (int s = 0; s < N; ++s) {
-                const double Uc = Un;
-                if (Up) Un = Up[s + 1 < N ? s + 1 : s];
-                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                       Dt[2 * s + 1], Dt[2 * s + 2]);
-                const double u = sample<NM, COMP>(x, cx, zc);
-                Sc += u * Lc[s + 1];
-                Ss += u * Ls[s + 1];
-                if (Up) {
-                    const double U = Uc * 1e9;
-                    const double e = U - u;
-                    Jn += e * e;
-                    Jd += U * U;
+                const double lc = Lc[s + 1], ls = Ls[s + 1];
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const double Uc = Un[t];
+                    if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
+                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
+                                           h6, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
+                    // explicit fmas: with contraction left to the compiler, instantiations
+                    // that differ only in lanes per trajectory could round differently
+                    const double u = sample<NM, COMP>(x[t], cx[t], zc[t]);
+                    Sc[t] = __builtin_fma(u, lc, Sc[t]);
+                    Ss[t] = __builtin_fma(u, ls, Ss[t]);
+                    if (Up[t]) {
+                        const double U = Uc * 1e9;
+                        const double e = U - u;
+                        Jn[t] = __builtin_fma(e, e, Jn[t]);
+                        Jd[t] = __builtin_fma(U, U, Jd[t]);
+                    }
+                    if (trow[t]) trow[t][w0 + s] = u * 1e-9;
                 }
-                if (trow) trow[w0 + s] = u * 1e-9;
             }
         }
         // end-of-period health check: every state entry finite and |u| within the limit
-        bool fin = true;
+        bool alive = false;
 #pragma unroll
-        for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[i]) && isfinite(v[i]);
-        if (!fin) {
-            st = AFM_ST_NONFINITE;
-            break;
+        for (int t = 0; t < T; ++t) {
+            if (!st[t]) {
+                bool fin = true;
+#pragma unroll
+                for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[t][i]) && isfinite(v[t][i]);
+                if (!fin) st[t] = AFM_ST_NONFINITE;
+                else if (fabs(sample<NM, COMP>(x[t], cx[t], zc[t])) > lim) st[t] = AFM_ST_DIVERGED;
+            }
+            alive = alive || !st[t];
         }
-        if (fabs(sample<NM, COMP>(x, cx, zc)) > lim) {
-            st = AFM_ST_DIVERGED;
-            break;
+        if (!alive) break;
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        o[t].st = st[t];
+        if (st[t]) {
+            o[t].A = NAN;
+            o[t].phi = NAN;
+            o[t].J = INFINITY;
+            if (trow[t])
+                for (int w = 0; w < K.lockin * N; ++w) trow[t][w] = NAN;
+        } else {
+            const double Wn = (double)K.lockin * N;
+            const double X = 2.0 * Sc[t] / Wn, Y = 2.0 * Ss[t] / Wn;
+            o[t].A = ::sqrt(__builtin_fma(X, X, Y * Y)) * 1e-9;
+            o[t].phi = ::atan2(-X, Y);
+            const double J = Urow[t] ? Jn[t] / Jd[t] : NAN;
+            o[t].J = (Urow[t] && !isfinite(J)) ? INFINITY : J;
         }
     }
-    LaneOut o;
-    o.st = st;
-    if (st) {
-        o.A = NAN;
-        o.phi = NAN;
-        o.J = INFINITY;
-        if (trow)
-            for (int w = 0; w < K.lockin * N; ++w) trow[w] = NAN;
-    } else {
-        const double Wn = (double)K.lockin * N;
-        const double X = 2.0 * Sc / Wn, Y = 2.0 * Ss / Wn;
-        o.A = ::sqrt(X * X + Y * Y) * 1e-9;
-        o.phi = ::atan2(-X, Y);
-        const double J = Urow ? Jn / Jd : NAN;
-        o.J = (Urow && !isfinite(J)) ? INFINITY : J;
-    }
-    return o;
 }
 
-// One lane's trajectory i (group grp): parameter load, bounds checks, integration, outputs.
-template <int LAW, int NM, bool MIXED, int FM>
-__device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K, int64_t i,
-                                             int64_t grp, int nc) {
+// One lane's T trajectories ii[t] (those with act[t] false only keep the lane's time loop
+// company and write nothing): parameter load, bounds checks, integration, outputs.  All T
+// trajectories run nc periods.
+template <int LAW, int NM, bool MIXED, int FM, int T>
+__device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
+                                             const int64_t (&ii)[T], const bool (&act)[T],
+                                             int nc) {
     using R = typename std::conditional<MIXED, float, double>::type;
-    double p[kMaxParams];
-    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
-    const Law<LAW, R> law(p, K);
     const int64_t W = (int64_t)K.lockin * K.N;
-    const double *Urow = nullptr;
-    bool bad = nc < K.lockin;
-    if (A.targets) {
-        const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : (A.row_by_group ? grp : 0);
-        bad = bad || row < 0 || row >= A.n_targets;
-        Urow = bad ? nullptr : A.targets + row * W;
+    Law<LAW, R> law[T];
+    double zc[T];
+    const double *Urow[T];
+    double *trow[T];
+    bool bad[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int64_t i = act[t] ? ii[t] : ii[0];
+        const int64_t grp = A.group > 0 ? i / A.group : i;
+        double p[kMaxParams];
+        load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+        law[t] = Law<LAW, R>(p, K);
+        zc[t] = p[0] * 1e9;
+        Urow[t] = nullptr;
+        bad[t] = nc < K.lockin;
+        if (A.targets) {
+            const int64_t row = A.target_id ? (int64_t)A.target_id[grp]
+                                            : (A.row_by_group ? grp : 0);
+            bad[t] = bad[t] || row < 0 || row >= A.n_targets;
+            Urow[t] = bad[t] ? nullptr : A.targets + row * W;
+        }
+        trow[t] = (A.trace && act[t]) ? A.trace + i * W : nullptr;
     }
-    double *trow = A.trace ? A.trace + i * W : nullptr;
-    LaneOut o;
-    if (bad) {
-        o.A = NAN;
-        o.phi = NAN;
-        o.J = INFINITY;
-        o.st = AFM_ST_BAD_INPUT;
-        if (trow)
-            for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
-    } else {
-        o = integrate<LAW, NM, MIXED, FM>(law, p[0] * 1e9, K, nc, Urow, trow);
+    bool all_bad = true;
+#pragma unroll
+    for (int t = 0; t < T; ++t) all_bad = all_bad && bad[t];
+    LaneOut o[T];
+    if (!all_bad) integrate<LAW, NM, MIXED, FM, T>(law, zc, K, nc, Urow, trow, o);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        if (!act[t]) continue;
+        if (bad[t]) {
+            o[t].A = NAN;
+            o[t].phi = NAN;
+            o[t].J = INFINITY;
+            o[t].st = AFM_ST_BAD_INPUT;
+            if (trow[t])
+                for (int64_t w = 0; w < W; ++w) trow[t][w] = NAN;
+        }
+        const int64_t i = ii[t];
+        if (A.amp) A.amp[i] = o[t].A;
+        if (A.phase) A.phase[i] = o[t].phi;
+        if (A.J) A.J[i] = o[t].J;
+        if (A.status) A.status[i] = o[t].st;
     }
-    if (A.amp) A.amp[i] = o.A;
-    if (A.phase) A.phase[i] = o.phi;
-    if (A.J) A.J[i] = o.J;
-    if (A.status) A.status[i] = o.st;
 }
 
-template <int LAW, int NM, bool MIXED, int FM>
+// T trajectories per lane: lane l of block b owns b B T + t B + l, t < T (coalesced per t).
+// With T > 1 the period count must be the plan's (no per-trajectory counts).
+template <int LAW, int NM, bool MIXED, int FM, int T>
 __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    const int64_t grp = A.group > 0 ? i / A.group : i;
-    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
-    lane_forward<LAW, NM, MIXED, FM>(A, K, i, grp, nc);
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * T + threadIdx.x;
+    if (i0 >= A.n) return;
+    int64_t ii[T];
+    bool act[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        ii[t] = i0 + (int64_t)t * blockDim.x;
+        act[t] = ii[t] < A.n;
+    }
+    int nc = K.n_cycles;
+    if constexpr (T == 1) {
+        const int64_t grp = A.group > 0 ? i0 / A.group : i0;
+        if (A.n_cycles) nc = A.n_cycles[grp];
+    }
+    lane_forward<LAW, NM, MIXED, FM, T>(A, K, ii, act, nc);
 }
 
 // Persistent work queue for batches of groups with uneven period counts (one pixel's swarm is
@@ -191,7 +266,11 @@ __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KC
         const int64_t local = (int64_t)(id % A.chunks) * 64 + lane;
         int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
         nc = __builtin_amdgcn_readfirstlane(nc);
-        if (local < A.group) lane_forward<LAW, NM, MIXED, FM>(A, K, grp * A.group + local, grp, nc);
+        if (local < A.group) {
+            const int64_t ii[1] = {grp * A.group + local};
+            const bool act[1] = {true};
+            lane_forward<LAW, NM, MIXED, FM, 1>(A, K, ii, act, nc);
+        }
     }
 }
 
@@ -199,68 +278,138 @@ __global__ void k_queue_reset(int32_t *head) {
     if (threadIdx.x == 0) *head = 0;
 }
 
-// Small batches (fewer waves than SIMDs) are issue-latency bound: one-wave blocks spread over
-// the CUs and the branch-free law minimises issue slots.  Large batches are throughput bound:
-// 4-wave blocks and the branching law (fewer transcendental ops).
+// Force-law form by regime (not tuned: the per-lane branching form rounds the in-contact
+// attraction differently, and tuning must never change results).  Small batches (fewer waves
+// than SIMDs) are issue-latency bound: the branch-free form needs the fewest issue slots.  Large
+// batches are throughput bound: the per-lane branch (fewer transcendental ops; other waves
+// hide its scalar instructions).
 constexpr int64_t kSmallBatch = 65536;
 
+// Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
 template <int LAW, int NM, bool MIXED>
-hipError_t launch_t(const FwdArgs &a, const KConst &K, int32_t n_cu, hipStream_t s) {
+hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStream_t s) {
+    constexpr bool branchy = Law<LAW, float>::kBranch;
+    const int64_t per_block = (int64_t)sh.block * sh.tpl;
+    const dim3 grid((unsigned)((a.n + per_block - 1) / per_block)), blk((unsigned)sh.block);
+    const bool large = branchy && a.n >= kSmallBatch;
+    if constexpr (NM == 1) {
+        if (sh.tpl == 2) {
+            if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 2>), grid, blk, 0, s, a, K);
+            else hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 2>), grid, blk, 0, s, a, K);
+            return hipGetLastError();
+        }
+    }
+    if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 1>), grid, blk, 0, s, a, K);
+    else hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1>), grid, blk, 0, s, a, K);
+    return hipGetLastError();
+}
+
+template <int LAW, int NM, bool MIXED>
+hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
     if (a.items) {
         // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one
         // swarm (one separation), so they enter contact together: the wave-uniform skip form
         // (measured 11 % faster here than the per-lane branching form)
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
-        const unsigned blocks = (unsigned)(n_cu > 0 ? n_cu : 256) * 4;
+        const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
         hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree>),
                            dim3(blocks), dim3(256), 0, s, a, K);
         return hipGetLastError();
     }
-    const int block = a.n < kSmallBatch ? 64 : 256;
-    const int64_t grid = (a.n + block - 1) / block;
-    if constexpr (branchy) {
-        if (a.n >= kSmallBatch) {
-            hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch>), dim3((unsigned)grid),
-                               dim3(block), 0, s, a, K);
-            return hipGetLastError();
-        }
-    }
-    hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree>), dim3((unsigned)grid), dim3(block), 0,
-                       s, a, K);
-    return hipGetLastError();
+    FwdShape sh;
+    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM == 1, s,
+                                 [&](FwdShape c) { return launch_plain<LAW, NM, MIXED>(a, K, c, s); },
+                                 &sh);
+    if (e != hipSuccess) return e;
+    return launch_plain<LAW, NM, MIXED>(a, K, sh, s);
 }
 
 template <int LAW, bool MIXED>
-hipError_t launch_modes(const FwdArgs &a, const KConst &K, int32_t cu, hipStream_t s) {
+hipError_t launch_modes(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     switch (K.nm) {
-    case 1: return launch_t<LAW, 1, MIXED>(a, K, cu, s);
-    case 2: return launch_t<LAW, 2, MIXED>(a, K, cu, s);
-    case 3: return launch_t<LAW, 3, MIXED>(a, K, cu, s);
-    case 4: return launch_t<LAW, 4, MIXED>(a, K, cu, s);
+    case 1: return launch_t<LAW, 1, MIXED>(plan, a, K, s);
+    case 2: return launch_t<LAW, 2, MIXED>(plan, a, K, s);
+    case 3: return launch_t<LAW, 3, MIXED>(plan, a, K, s);
+    case 4: return launch_t<LAW, 4, MIXED>(plan, a, K, s);
     }
     return hipErrorInvalidValue;
 }
 
 template <bool MIXED>
-hipError_t launch_law(const FwdArgs &a, const KConst &K, int32_t cu, hipStream_t s) {
+hipError_t launch_law(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     switch (K.law) {
-    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(a, K, cu, s);
-    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(a, K, cu, s);
-    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(a, K, cu, s);
-    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(a, K, cu, s);
-    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(a, K, cu, s);
-    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(a, K, cu, s);
+    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(plan, a, K, s);
+    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(plan, a, K, s);
+    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(plan, a, K, s);
+    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(plan, a, K, s);
+    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(plan, a, K, s);
+    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(plan, a, K, s);
     }
     return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+// Launch shape of a plain forward launch: the plan's tuned choice for this precision, batch
+// size and period-count mode; tuned on first use (every candidate timed once on the real
+// arguments, after one warm-up launch) unless the stream is being captured, in which case the
+// default shape is used (one-wave blocks for small batches, four-wave blocks for large ones,
+// one trajectory per lane).  Every candidate computes bit-identical results, so tuning never
+// changes an output.
+hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, bool pair_ok,
+                         hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
+                         FwdShape *out) {
+    const int32_t has_nc = a.n_cycles != nullptr;
+    if (plan->pinned_shape.block > 0) {
+        *out = plan->pinned_shape;
+        if (!(pair_ok && !has_nc)) out->tpl = 1;
+        return hipSuccess;
+    }
+    for (const FwdTune &t : plan->fwd_tune)
+        if (t.n == a.n && t.prec == prec && t.has_nc == has_nc) {
+            *out = t.shape;
+            return hipSuccess;
+        }
+    FwdShape def{a.n < kSmallBatch ? 64 : 256, 1};
+    *out = def;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    std::vector<FwdShape> cand;
+    for (int b : {64, 128, 256}) {
+        cand.push_back({b, 1});
+        if (pair_ok && !has_nc) cand.push_back({b, 2});
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch(def);  // warm-up (code load, caches)
+    float best = 0.0f;
+    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch(cand[k]);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (k == 0 || ms < best)) {
+            best = ms;
+            *out = cand[k];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    plan->fwd_tune.push_back({a.n, prec, has_nc, *out, best});
+    return hipSuccess;
+}
+
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    if (prec == AFM_PREC_MIXED) return launch_law<true>(a, plan->kc, plan->n_cu, s);
-    return launch_law<false>(a, plan->kc, plan->n_cu, s);
+    if (prec == AFM_PREC_MIXED) return launch_law<true>(plan, a, plan->kc, s);
+    return launch_law<false>(plan, a, plan->kc, s);
 }
 
 hipError_t launch_forward(const afm_plan *plan, const FwdArgs &a, hipStream_t s) {

@@ -159,12 +159,6 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         if (e != hipSuccess) return hip_fail(e, "afm_invert queue upload");
     }
     if (!hit) {
-        release_graph(plan);
-        g = new GraphCache();
-        plan->graph = g;
-        e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "afm_invert capture begin");
-        e = launch_swarm_init(plan, sw, seed, plan->stream);
         FwdArgs a{};
         a.n = (int64_t)n_swarms * particles;
         a.ld = a.n;
@@ -184,6 +178,22 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         }
         a.J = J;
         a.status = status;
+        if (!n_cycles) {
+            // the captured forward launches take whatever launch shape the plan holds for this
+            // batch size, so let it be tuned first: an eager swarm init and forward, ordered
+            // after the caller's earlier work (the graph repeats both)
+            e = hipEventRecord(plan->ev_in, (hipStream_t)stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in, 0);
+            if (e == hipSuccess) e = launch_swarm_init(plan, sw, seed, plan->stream);
+            if (e == hipSuccess) e = launch_forward(plan, a, plan->stream);
+            if (e != hipSuccess) return hip_fail(e, "afm_invert launch-shape tuning");
+        }
+        release_graph(plan);
+        g = new GraphCache();
+        plan->graph = g;
+        e = hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "afm_invert capture begin");
+        e = launch_swarm_init(plan, sw, seed, plan->stream);
         for (int32_t t = 0; t < iters && e == hipSuccess; ++t) {
             e = launch_forward(plan, a, plan->stream);
             if (e == hipSuccess)

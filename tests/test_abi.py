@@ -103,3 +103,10 @@ def test_bad_precision_and_null_arguments(afm):
     assert afm.lib().afm_plan_create(None, 0, C.byref(h)) == 1
     assert afm.lib().afm_forward_batch(None, 1, None, None, None, None, None, None, None) == 1
     assert afm.lib().afm_plan_destroy(None) == 0
+
+
+def test_launch_shape_arguments_checked(afm):
+    """afm_set_launch_shape validates before touching the plan (no GPU needed for the rejects)."""
+    L = afm.lib()
+    assert L.afm_set_launch_shape(None, 64, 1) == 1
+    assert afm.lib().afm_last_error().decode()

@@ -286,3 +286,41 @@ def test_steps_per_period_edges_mixed(afm, orc, N):
     o = PT.oracle_batch(orc, m, P)
     failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, tag=f"N={N}")
     assert not failing and len(excluded) <= 2
+
+
+@pytest.mark.parametrize("precision,n,nc", [("mixed", 1000, 60), ("fp64", 333, 40),
+                                            ("mixed", 70000, 24)])
+def test_launch_shapes_bit_identical(afm, orc, precision, n, nc):
+    """Every launch shape (64 / 128 / 256 lanes x 1 / 2 trajectories per lane) gives the same
+    bits as the autotuned launch, on ragged batches (partial workgroups, half-filled lane
+    pairs) below and above the large-batch switch; sampled trajectories match the oracle."""
+    import torch
+
+    c = W.config("c2")
+    m = dict(c["model"], n_cycles=nc)
+    U = orc.forward(m, W.full_params(c), want_trace=True)["trace"]
+    plan = _plan(afm, c, precision, model=m)
+    th = torch.tensor(_theta(c, n, 40 + n), device="cuda")
+    ref_J, ref_st = (x.cpu().numpy() for x in plan.misfit(th, U[None, :]))
+    ref = {k: v.cpu().numpy() for k, v in plan.forward_batch(th, trace=n <= 1000).items()
+           if v is not None}
+    for block in (64, 128, 256):
+        for tpl in (1, 2):
+            plan.set_launch_shape(block, tpl)
+            J, st = (x.cpu().numpy() for x in plan.misfit(th, U[None, :]))
+            assert np.array_equal(J.view(np.uint64), ref_J.view(np.uint64)), (block, tpl)
+            assert np.array_equal(st, ref_st), (block, tpl)
+            r = plan.forward_batch(th, trace=n <= 1000)
+            for k, v in r.items():
+                if v is None:
+                    continue
+                a = v.cpu().numpy()
+                assert np.array_equal(a.view(np.uint8), ref[k].view(np.uint8)), (block, tpl, k)
+    plan.set_launch_shape(0)
+    idx = np.random.default_rng(n).choice(n, 12, replace=False)
+    P = PT.full_from_free(W.full_params(c), W.free_index(c), th.cpu().numpy()[:, idx])
+    o = PT.oracle_batch(orc, m, P, target=U)
+    assert np.array_equal(ref_st[idx], o["status"])
+    tol = (lambda Jo: 1e-9 * Jo + 1e-15) if precision == "fp64" else PT.misfit_tol
+    for k in np.flatnonzero(np.abs(ref_J[idx] - o["J"]) > tol(o["J"])):
+        assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
