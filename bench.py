@@ -225,6 +225,41 @@ def time_to_inversion(afm, W, dev, U, cfg):
     return res
 
 
+def plain_method_leg(afm, W, dev):
+    """c1: the plain method in FP64 -- 2 parameters (H, E*), 32 particles x 20 generations,
+    100 periods x 200 steps, noiseless target (plain FP64 forward at the truth); whole
+    inversions as graph replays, with the recovered parameters' errors."""
+    import torch
+
+    cfg = W.config("c1")
+    m, free, base = cfg["model"], W.free_index(cfg), W.full_params(cfg)
+    truth = [cfg["truth"]["H"], cfg["truth"]["Estar"]]
+    ref = afm.Plan(m, base, free, precision="fp64", device=dev)
+    U = ref.forward_batch(torch.tensor([[t] for t in truth], device=dev),
+                          trace=True)["trace"].contiguous()
+    res = {"workload": "c1: point-mass DMT, invert (H, E*), 32 particles x 20 generations, "
+                       "100 periods x 200 steps, noiseless"}
+    for prec in ("fp64", "mixed"):
+        plan = afm.Plan(m, base, free, precision=prec, device=dev)
+        P, T = int(cfg["particles"]), int(cfg["iters"])
+        plan.invert(U, P, T, seed=cfg["seed"], cutoff=1e-2)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = plan.invert(U, P, T, seed=cfg["seed"], cutoff=1e-2)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        bt = out["best_theta"].cpu().numpy()[:, 0]
+        res[prec] = {"ms_per_inversion": dt * 1e3,
+                     "rk4_steps_per_s": P * T * m["n_cycles"] * m["steps_per_cycle"] / dt,
+                     "best_J": float(out["best_J"].item()),
+                     "generation_reaching_sqrtJ_0.01": int(out["gen_to_cutoff"].item()),
+                     "rel_error_H": abs(bt[0] / truth[0] - 1),
+                     "rel_error_Estar": abs(bt[1] / truth[1] - 1)}
+    return res
+
+
 def gradient_leg(afm, W, dev):
     """c4: discrete-adjoint gradients of 2048 Lennard-Jones-type points, 1000 periods x 256
     steps, at each checkpoint stride."""
@@ -484,6 +519,7 @@ def main():
     if not args.no_more:
         line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg)
         line["time_to_inversion_pixels"] = pixel_time_to_inversion(afm, W, dev, 256, cutoff=1e-3)
+        line["plain_method"] = plain_method_leg(afm, W, dev)
         line["gradients"] = gradient_leg(afm, W, dev)
         line["three_mode"] = three_mode_leg(afm, W, dev, 2)
     if not args.no_cpu_baseline:

@@ -140,13 +140,16 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * evaluations of afm_invert without per-swarm period counts, polish line searches).  By default
  * (block = 0) it is autotuned per precision, batch size and period-count mode: the first call
  * with a new combination runs the launch once per candidate -- workgroups of 64, 128 or 256
- * lanes, one or two trajectories per lane (two only for point-mass problems without
- * per-trajectory period counts) -- times each with events and keeps the fastest; that call
- * synchronises the stream.  Under stream capture nothing is timed and the default shape is used
- * (64 lanes below 65536 trajectories, else 256; one trajectory per lane).  afm_invert tunes
- * before it captures.  Every shape computes bit-identical results.
- * block in {64, 128, 256} and tpl in {1, 2} pin the shape for this plan (tpl 2 falls back to 1
- * where it does not apply); block = 0 returns to tuning.  Anything else: AFM_ERR_INVALID. */
+ * lanes, times one trajectory per lane, two trajectories per lane (point-mass problems without
+ * per-trajectory period counts) or one lane per mode (problems with several modes: 2 lanes per
+ * trajectory for 2 modes, 4 for 3 or 4; the paper's mapping of modes to threads, Sec. 3.2) --
+ * times each with events and keeps the fastest; that call synchronises the stream.  Under stream
+ * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,
+ * else 256; one trajectory per lane).  afm_invert tunes before it captures.  Every shape
+ * computes bit-identical results.
+ * block in {64, 128, 256} and tpl in {1, 2, 0} (0 = one lane per mode) pin the shape for this
+ * plan (a tpl that does not apply falls back to 1); block = 0 returns to tuning.  Anything
+ * else: AFM_ERR_INVALID. */
 afm_status afm_set_launch_shape(afm_plan *plan, int32_t block, int32_t tpl);
 
 /* FP for n parameter points.  theta: [n_free][n] SI values of the free parameters (device).

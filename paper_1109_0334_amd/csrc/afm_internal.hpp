@@ -450,7 +450,7 @@ namespace afm {
 // Launch shape of a plain forward launch and the plan's record of tuned shapes.
 struct FwdShape {
     int32_t block;  // lanes per workgroup: 64, 128 or 256
-    int32_t tpl;    // trajectories per lane: 1 or 2
+    int32_t tpl;    // trajectories per lane: 1 or 2; 0 = mode-parallel (one lane per mode)
 };
 struct FwdTune {
     int64_t n;       // batch size
@@ -528,7 +528,7 @@ hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, 
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
 // tuned (or, under stream capture, default) shape of a plain forward launch; `launch` runs one
 // candidate on the real arguments
-hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, bool pair_ok,
+hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, int nm,
                          hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
                          FwdShape *out);
 size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);

@@ -196,9 +196,9 @@ afm_status afm_set_launch_shape(afm_plan *plan, int32_t block, int32_t tpl) {
         plan->pinned_shape = afm::FwdShape{0, 0};
         return AFM_OK;
     }
-    if (!(block == 64 || block == 128 || block == 256) || !(tpl == 1 || tpl == 2))
+    if (!(block == 64 || block == 128 || block == 256) || !(tpl == 0 || tpl == 1 || tpl == 2))
         return fail(AFM_ERR_INVALID, "afm_set_launch_shape: block must be 0, 64, 128 or 256 and "
-                                     "tpl 1 or 2");
+                                     "tpl 0, 1 or 2");
     plan->pinned_shape = afm::FwdShape{block, tpl};
     return AFM_OK;
 }

@@ -248,6 +248,157 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
     lane_forward<LAW, NM, MIXED, FM, T>(A, K, ii, act, nc);
 }
 
+// Mode-parallel forward: G lanes per trajectory (G = 2 for two modes, 4 for three or four),
+// lane q integrating mode q with the shared force (rk4_step_mp).  Same operations in the same
+// order as the one-lane kernel, so the same bits; the time loops, health checks and window
+// sums are group-uniform (every lane of a group sees the same gap, deflection and flags).
+template <int LAW, int NM, bool MIXED, int FM>
+__device__ __forceinline__ LaneOut integrate_mp(
+    const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
+    const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow, int q,
+    int gbase) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    constexpr bool COMP = MIXED;
+    constexpr int G = NM <= 2 ? 2 : 4;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    const double *__restrict__ Lc = K.lock_c;
+    const double *__restrict__ Ls = K.lock_s;
+
+    ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
+    R x = R(0), v = R(0), cx = R(0), cv = R(0);
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        if (q == i) {
+            ml.om2 = (R)K.om2[i];
+            ml.cd = (R)K.cdamp[i];
+            ml.gn = (R)K.gain[i];
+            ml.zoff = i == 0 ? law.zc : R(0);
+            ml.w = R(1);
+            x = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
+            v = (R)K.y0[NM + i];
+        }
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    const int N = K.N;
+    const int c_win = nc - K.lockin;
+    const double lim = K.div_nm;
+    double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+
+    for (int c = 0; c < nc; ++c) {
+        if (c < c_win) {
+            int s = 0;
+            for (; s + 4 <= N; s += 4) {
+                using CR = const __attribute__((address_space(4))) R;
+                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
+                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e0, e1, e2);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e2, e3, e4);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e4, e5, e6);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e6, e7, e8);
+            }
+            for (; s < N; ++s)
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                                             Dt[2 * s + 1], Dt[2 * s + 2]);
+        } else {
+            const int w0 = (c - c_win) * N;
+            const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
+            double Un = Up ? Up[0] : 0.0;
+            for (int s = 0; s < N; ++s) {
+                const double Uc = Un;
+                if (Up) Un = Up[s + 1 < N ? s + 1 : s];
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                                             Dt[2 * s + 1], Dt[2 * s + 2]);
+                const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
+                Sc = __builtin_fma(u, Lc[s + 1], Sc);
+                Ss = __builtin_fma(u, Ls[s + 1], Ss);
+                if (Up) {
+                    const double U = Uc * 1e9;
+                    const double e = U - u;
+                    Jn = __builtin_fma(e, e, Jn);
+                    Jd = __builtin_fma(U, U, Jd);
+                }
+                if (trow && q == 0) trow[w0 + s] = u * 1e-9;
+            }
+        }
+        // end-of-period health check, combined over the group
+        int nonfinite = !(isfinite(x) && isfinite(v));
+        nonfinite |= __shfl_xor(nonfinite, 1, 64);
+        if constexpr (G == 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
+        if (nonfinite) {
+            st = AFM_ST_NONFINITE;
+            break;
+        }
+        if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > lim) {
+            st = AFM_ST_DIVERGED;
+            break;
+        }
+    }
+    LaneOut o;
+    o.st = st;
+    if (st) {
+        o.A = NAN;
+        o.phi = NAN;
+        o.J = INFINITY;
+        if (trow && q == 0)
+            for (int w = 0; w < K.lockin * N; ++w) trow[w] = NAN;
+    } else {
+        const double Wn = (double)K.lockin * N;
+        const double X = 2.0 * Sc / Wn, Y = 2.0 * Ss / Wn;
+        o.A = ::sqrt(__builtin_fma(X, X, Y * Y)) * 1e-9;
+        o.phi = ::atan2(-X, Y);
+        const double J = Urow ? Jn / Jd : NAN;
+        o.J = (Urow && !isfinite(J)) ? INFINITY : J;
+    }
+    return o;
+}
+
+// G lanes per trajectory; the block size is a multiple of 4, so groups never straddle a
+// workgroup and every lane of a group exits together.
+template <int LAW, int NM, bool MIXED, int FM>
+__global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    constexpr int G = NM <= 2 ? 2 : 4;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= A.n) return;
+    const int q = threadIdx.x & (G - 1);
+    const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const Law<LAW, R> law(p, K);
+    const int64_t W = (int64_t)K.lockin * K.N;
+    const double *Urow = nullptr;
+    bool bad = nc < K.lockin;
+    if (A.targets) {
+        const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : (A.row_by_group ? grp : 0);
+        bad = bad || row < 0 || row >= A.n_targets;
+        Urow = bad ? nullptr : A.targets + row * W;
+    }
+    double *trow = A.trace ? A.trace + i * W : nullptr;
+    LaneOut o;
+    if (bad) {
+        o.A = NAN;
+        o.phi = NAN;
+        o.J = INFINITY;
+        o.st = AFM_ST_BAD_INPUT;
+        if (trow && q == 0)
+            for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
+    } else {
+        o = integrate_mp<LAW, NM, MIXED, FM>(law, p[0] * 1e9, K, nc, Urow, trow, q, gbase);
+    }
+    if (q == 0) {
+        if (A.amp) A.amp[i] = o.A;
+        if (A.phase) A.phase[i] = o.phi;
+        if (A.J) A.J[i] = o.J;
+        if (A.status) A.status[i] = o.st;
+    }
+}
+
 // Persistent work queue for batches of groups with uneven period counts (one pixel's swarm is
 // one group).  Each wavefront repeatedly takes the next item -- 64 lanes of one group -- from a
 // queue ordered longest first, until the queue is empty; every wave reaches the exit.  The
@@ -292,6 +443,16 @@ hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStrea
     const int64_t per_block = (int64_t)sh.block * sh.tpl;
     const dim3 grid((unsigned)((a.n + per_block - 1) / per_block)), blk((unsigned)sh.block);
     const bool large = branchy && a.n >= kSmallBatch;
+    if constexpr (NM > 1) {
+        if (sh.tpl == 0) {  // mode-parallel: G lanes per trajectory
+            constexpr int G = NM <= 2 ? 2 : 4;
+            const int64_t per = sh.block / G;
+            const dim3 g2((unsigned)((a.n + per - 1) / per));
+            if (large) hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmBranch>), g2, blk, 0, s, a, K);
+            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree>), g2, blk, 0, s, a, K);
+            return hipGetLastError();
+        }
+    }
     if constexpr (NM == 1) {
         if (sh.tpl == 2) {
             if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 2>), grid, blk, 0, s, a, K);
@@ -318,7 +479,7 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
         return hipGetLastError();
     }
     FwdShape sh;
-    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM == 1, s,
+    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM, s,
                                  [&](FwdShape c) { return launch_plain<LAW, NM, MIXED>(a, K, c, s); },
                                  &sh);
     if (e != hipSuccess) return e;
@@ -357,13 +518,14 @@ hipError_t launch_law(const afm_plan *plan, const FwdArgs &a, const KConst &K, h
 // default shape is used (one-wave blocks for small batches, four-wave blocks for large ones,
 // one trajectory per lane).  Every candidate computes bit-identical results, so tuning never
 // changes an output.
-hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, bool pair_ok,
+hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, int nm,
                          hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
                          FwdShape *out) {
     const int32_t has_nc = a.n_cycles != nullptr;
+    const bool pair_ok = nm == 1 && !has_nc;
     if (plan->pinned_shape.block > 0) {
         *out = plan->pinned_shape;
-        if (!(pair_ok && !has_nc)) out->tpl = 1;
+        if ((out->tpl == 2 && !pair_ok) || (out->tpl == 0 && nm == 1)) out->tpl = 1;
         return hipSuccess;
     }
     for (const FwdTune &t : plan->fwd_tune)
@@ -380,7 +542,8 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, b
     std::vector<FwdShape> cand;
     for (int b : {64, 128, 256}) {
         cand.push_back({b, 1});
-        if (pair_ok && !has_nc) cand.push_back({b, 2});
+        if (pair_ok) cand.push_back({b, 2});
+        if (nm > 1) cand.push_back({b, 0});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     e = hipEventCreate(&e0);

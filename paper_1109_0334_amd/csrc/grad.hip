@@ -47,12 +47,8 @@ __device__ __forceinline__ void stage_eval(const L &law, const R (&x)[NM], const
                                            const R (&om2)[NM], const R (&cd)[NM],
                                            const R (&gn)[NM], R D, R (&a)[NM], R &Fd, R &Fdd,
                                            R (&dc)[L::NC]) {
-    R d = x[0];
-#pragma unroll
-    for (int i = 1; i < NM; ++i) d += x[i];
-    R dd = v[0];
-#pragma unroll
-    for (int i = 1; i < NM; ++i) dd += v[i];
+    const R d = mode_sum<NM>(x);
+    const R dd = mode_sum<NM>(v);
     const R F = law.grad(d, dd, Fd, Fdd, dc);
     if constexpr (NM == 1) {
         a[0] = Ops<R>::fma(-om2[0], x[0] - law.zc, Ops<R>::fma(-cd[0], v[0], F + D));

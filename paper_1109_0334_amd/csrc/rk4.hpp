@@ -12,20 +12,30 @@ namespace afm {
 // (forming z_c + x_1 from two ~A0-sized numbers would lose it).  The restoring force of mode 1
 // uses x_1 = g - z_c, which needs only absolute precision.
 //
+// Sum over modes in the order a butterfly over the lanes of a mode-parallel group produces:
+// sequential up to three modes ((x0 + x1) + x2, the missing fourth lane adding an exact zero),
+// pairwise for four.  The one-lane and the mode-parallel kernels use this same order, so they
+// compute identical bits.
+template <int NM, typename R>
+__device__ __forceinline__ R mode_sum(const R (&x)[NM]) {
+    if constexpr (NM == 4) {
+        return (x[0] + x[1]) + (x[2] + x[3]);
+    } else {
+        R d = x[0];
+#pragma unroll
+        for (int i = 1; i < NM; ++i) d += x[i];
+        return d;
+    }
+}
+
 // Slopes of the modal system at state (g, x_2.., v_1..): returns the accelerations a_i.
 template <int NM, int FM, typename R, class L>
 __device__ __forceinline__ void accel(const L &law, const R (&x)[NM], const R (&v)[NM],
                                       const R (&om2)[NM], const R (&cd)[NM], const R (&gn)[NM],
                                       R D, R (&a)[NM]) {
-    R d = x[0];
-#pragma unroll
-    for (int i = 1; i < NM; ++i) d += x[i];
+    const R d = mode_sum<NM>(x);
     R dd = R(0);
-    if constexpr (L::kRate) {
-        dd = v[0];
-#pragma unroll
-        for (int i = 1; i < NM; ++i) dd += v[i];
-    }
+    if constexpr (L::kRate) dd = mode_sum<NM>(v);
     if constexpr (NM == 1) {
         // point mass: the drive table already carries the mode's gain.  The restoring term keeps
         // its own (g - z_c): folding om2 z_c into the drive values instead would round the small
@@ -105,6 +115,113 @@ __device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM], do
     for (int i = 0; i < NM; ++i) {
         u += (double)x[i];
         if constexpr (COMP) u -= (double)cx[i];
+    }
+    return u;
+}
+
+// ------------------------------------------------------------------------------------------
+// Mode-parallel form (the paper's own mapping of modes to threads, Sec. 3.2): the G lanes of a
+// group (G = 2 for two modes, 4 for three or four) hold one trajectory, lane q its mode q (a
+// lane without a mode carries an exact zero).  The gap and gap rate are butterfly sums over the
+// group (DPP lane swaps, so the sum costs one add per butterfly level); every lane evaluates the
+// force law on the same sums and advances only its own mode.
+
+// Butterfly sum over the G lanes of a group; every lane gets the same bits.
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+    // quad_perm [1,0,3,2] swaps neighbours, [2,3,0,1] swaps pairs
+    float s = v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                      0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    if constexpr (G == 4)
+        s = s + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                    0, __builtin_bit_cast(int, s), 0x4E, 0xF, 0xF, false));
+    return s;
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double a) {
+    const long long b = __builtin_bit_cast(long long, a);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned int)hi << 32) |
+                                                  (unsigned int)lo));
+}
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    double s = v + dpp_swap<0xB1>(v);
+    if constexpr (G == 4) s = s + dpp_swap<0x4E>(s);
+    return s;
+}
+
+// One lane's mode constants: the restoring, damping and drive coefficients of its mode, the
+// offset of its coordinate (z_c for mode 1, carried as the gap) and the force weight (1 for a
+// real mode, 0 for a lane without one).
+template <typename R>
+struct ModeLane {
+    R om2, cd, gn, zoff, w;
+};
+
+template <int NM, int G, int FM, typename R, class L>
+__device__ __forceinline__ R accel_mp(const L &law, const ModeLane<R> &ml, R x, R v, R D) {
+    const R d = group_sum<G>(x);
+    R dd = R(0);
+    if constexpr (L::kRate) dd = group_sum<G>(v);
+    R F = law.template add<FM>(d, dd, R(0));
+    if constexpr (NM < G) F *= ml.w;
+    return Ops<R>::fma(-ml.om2, x - ml.zoff, Ops<R>::fma(-ml.cd, v, Ops<R>::fma(ml.gn, D, F)));
+}
+
+// The RK4 step of rk4_step for this lane's mode (same operations, same order).
+template <int NM, int G, bool COMP, int FM, typename R, class L>
+__device__ __forceinline__ void rk4_step_mp(const L &law, const ModeLane<R> &ml, R &x, R &v,
+                                            R &cx, R &cv, R h, R h2, R h6, R D0, R D1, R D2) {
+    R a = accel_mp<NM, G, FM>(law, ml, x, v, D0);
+    R sx = v, sv = a;
+    R xs = Ops<R>::fma(h2, v, x), vs = Ops<R>::fma(h2, a, v);
+    a = accel_mp<NM, G, FM>(law, ml, xs, vs, D1);
+    {
+        const R kx = vs;
+        sx = Ops<R>::fma(R(2), kx, sx);
+        sv = Ops<R>::fma(R(2), a, sv);
+        xs = Ops<R>::fma(h2, kx, x);
+        vs = Ops<R>::fma(h2, a, v);
+    }
+    a = accel_mp<NM, G, FM>(law, ml, xs, vs, D1);
+    {
+        const R kx = vs;
+        sx = Ops<R>::fma(R(2), kx, sx);
+        sv = Ops<R>::fma(R(2), a, sv);
+        xs = Ops<R>::fma(h, kx, x);
+        vs = Ops<R>::fma(h, a, v);
+    }
+    a = accel_mp<NM, G, FM>(law, ml, xs, vs, D2);
+    sx += vs;
+    sv += a;
+    if constexpr (COMP) {
+        const R dx = Ops<R>::fma(h6, sx, -cx);
+        const R tx = x + dx;
+        cx = (tx - x) - dx;
+        x = tx;
+        const R dv = Ops<R>::fma(h6, sv, -cv);
+        const R tv = v + dv;
+        cv = (tv - v) - dv;
+        v = tv;
+    } else {
+        x = Ops<R>::fma(h6, sx, x);
+        v = Ops<R>::fma(h6, sv, v);
+    }
+}
+
+// The tip deflection of `sample` from the group's lanes (gathered; the same sequence of FP64
+// additions), identical in every lane of the group.
+template <int NM, bool COMP, typename R>
+__device__ __forceinline__ double sample_mp(R x, R cx, double zc, int group_base) {
+    double u = -zc;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        u += (double)__shfl(x, group_base + i, 64);
+        if constexpr (COMP) u -= (double)__shfl(cx, group_base + i, 64);
     }
     return u;
 }

@@ -324,3 +324,42 @@ def test_launch_shapes_bit_identical(afm, orc, precision, n, nc):
     tol = (lambda Jo: 1e-9 * Jo + 1e-15) if precision == "fp64" else PT.misfit_tol
     for k in np.flatnonzero(np.abs(ref_J[idx] - o["J"]) > tol(o["J"])):
         assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
+
+
+@pytest.mark.parametrize("nm,law", [(2, "dmt"), (3, "kv"), (4, "kv")])
+def test_mode_parallel_bit_identical(afm, orc, nm, law):
+    """Mode-parallel launches (one lane per mode, butterfly sums over the group) give the same
+    bits as one lane per trajectory, on a ragged batch (partial workgroups); sampled points
+    match the oracle."""
+    import torch
+
+    c = W.config("c5")
+    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
+    m = dict(c["model"], law=law, n_modes=nm, q=[400.0] * nm,
+             ratio=[1.0, 6.27, 17.55, 34.39][:nm], gain=gains, n_cycles=60)
+    npar = 5 if law == "dmt" else 6
+    base = W.full_params(c)[:npar]
+    free = [f for f in W.free_index(c) if f[0] < npar]
+    rng = np.random.default_rng(50 + nm)
+    n = 333
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), n)) if f[3] else
+                   rng.uniform(f[1], f[2], n) for f in free])
+    U = orc.forward(m, base, want_trace=True)["trace"]
+    plan = afm.Plan(m, base, free, precision="mixed")
+    thd = torch.tensor(th, device="cuda")
+    plan.set_launch_shape(64, 1)
+    ref_J = plan.misfit(thd, U[None, :])[0].cpu().numpy()
+    ref = {k: v.cpu().numpy() for k, v in plan.forward_batch(thd, trace=True).items()}
+    for block in (64, 128, 256):
+        plan.set_launch_shape(block, 0)
+        J = plan.misfit(thd, U[None, :])[0].cpu().numpy()
+        assert np.array_equal(J.view(np.uint64), ref_J.view(np.uint64)), block
+        r = plan.forward_batch(thd, trace=True)
+        for k, v in r.items():
+            assert np.array_equal(v.cpu().numpy().view(np.uint8), ref[k].view(np.uint8)), (block, k)
+    idx = rng.choice(n, 6, replace=False)
+    P = PT.full_from_free(base, free, th[:, idx])
+    o = PT.oracle_batch(orc, m, P)
+    failing, excluded = PT.compare_mixed(orc, m, P, o, ref["amp"][idx], ref["phase"][idx],
+                                         ref["status"][idx], tag=f"{nm}-mode {law}")
+    assert not failing and len(excluded) <= 1
