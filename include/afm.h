@@ -216,7 +216,10 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
  * generations: init, then T x [misfit of every particle -> PSO generation]; then, if
  * lbfgs_steps > 0, the lbfgs_topk best personal bests of every swarm are polished by
  * afm_polish and the best polished point replaces the swarm best when lower.  Captured once as
- * a HIP graph and replayed without host round-trips.  targets: [S][W] (device); n_cycles: [S]
+ * a HIP graph and replayed without host round-trips: a later call with the same S, P, T, seed,
+ * cutoff, polish settings and input buffers (targets, n_cycles, swarm_params) replays it, with
+ * any output buffers; a new graph first tunes the forward launch shape (afm_set_launch_shape)
+ * unless the plan holds one for S*P trajectories.  targets: [S][W] (device); n_cycles: [S]
  * per-target period counts or NULL (uneven counts run through the persistent work-queue
  * kernel, longest first).  Outputs (device): best_theta [n_free][S] SI, best_J [S],
  * gen_to_cutoff [S].  swarm_params: [AFM_MAX_PARAMS][S] full parameter vectors per target

@@ -253,35 +253,66 @@ template <typename R> struct Law<AFM_LAW_LJ, R> {
 template <typename R> struct Law<AFM_LAW_KV, R> {
     static constexpr bool kRate = true;
     static constexpr bool kBranch = true;
-    R zc, a0, BH, BHa, BE, BV;
+    // FP32 form of the contact piece as for DMT: with q = ce (a0 - d) clamped by a median
+    // (ce = sgn(BE) |BE|^{2/3}, |ce| >= 1e-30 so that E* = 0 stays finite), the Hertz and
+    // viscous terms are sqrt(|q|) (q + BVs d') with BVs = BV / sqrt(|ce|).
+    R zc, a0, BH, BHa, BE, BV, ce, cea0, clim, BVs;
     Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
         const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
+        const double be = K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k;
+        const double bv = -K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k;
         zc = (R)(p[0] * 1e9);
         a0 = (R)a0n;
         BH = (R)bh;
         BHa = (R)(bh / (a0n * a0n));
-        BE = (R)(K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k);
-        BV = (R)(-K.G * p[5] * K.wd * ::sqrt(p[4]) * kSqrtNano / K.k);
+        BE = (R)be;
+        BV = (R)bv;
+        const double m = ::fmax(::cbrt(be * be), 1e-30);
+        const double c = be < 0.0 ? -m : m;
+        ce = (R)c;
+        cea0 = (R)(c * a0n);
+        clim = be < 0.0 ? -(R)INFINITY : (R)INFINITY;
+        BVs = (R)(bv / ::sqrt(m));
     }
     template <int FM> __device__ inline R add(R d, R dd, R b) const {
-        if constexpr (FM != kFmBranch) {
-            const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
-            const R del = Ops<R>::max(a0 - d, R(0));
-            return Ops<R>::fma(Ops<R>::sqrt(del), Ops<R>::fma(BE, del, BV * dd),
-                               Ops<R>::fma(BH * r, r, b));
-        } else {
-            R f;
-            if (d > a0) {
-                const R r = Ops<R>::rcp(d);
-                f = Ops<R>::fma(BH * r, r, b);
+        if constexpr (std::is_same<R, float>::value) {
+            if constexpr (FM != kFmBranch) {
+                const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
+                const R q = __builtin_amdgcn_fmed3f(Ops<R>::fma(-ce, d, cea0), R(0), clim);
+                return Ops<R>::fma(Ops<R>::sqrt(__builtin_fabsf(q)), Ops<R>::fma(BVs, dd, q),
+                                   Ops<R>::fma(BH * r, r, b));
             } else {
-                const R del = a0 - d;
-                const R s = Ops<R>::sqrt(del);
-                f = Ops<R>::fma(s, Ops<R>::fma(BE, del, BV * dd), b + BHa);
+                R f;
+                if (d > a0) {
+                    const R r = Ops<R>::rcp(d);
+                    f = Ops<R>::fma(BH * r, r, b);
+                } else {
+                    const R q = Ops<R>::fma(-ce, d, cea0);
+                    f = Ops<R>::fma(Ops<R>::sqrt(__builtin_fabsf(q)), Ops<R>::fma(BVs, dd, q),
+                                    b + BHa);
+                }
+                return f;
             }
-            return f;
+        } else {
+            if constexpr (FM != kFmBranch) {
+                const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+                const R del = Ops<R>::max(a0 - d, R(0));
+                return Ops<R>::fma(Ops<R>::sqrt(del), Ops<R>::fma(BE, del, BV * dd),
+                                   Ops<R>::fma(BH * r, r, b));
+            } else {
+                R f;
+                if (d > a0) {
+                    const R r = Ops<R>::rcp(d);
+                    f = Ops<R>::fma(BH * r, r, b);
+                } else {
+                    const R del = a0 - d;
+                    const R s = Ops<R>::sqrt(del);
+                    f = Ops<R>::fma(s, Ops<R>::fma(BE, del, BV * dd), b + BHa);
+                }
+                return f;
+            }
         }
     }
 
@@ -526,6 +557,8 @@ hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double 
 hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s);
 hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s);
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
+// whether the plan already holds a (tuned or pinned) shape for this plain forward launch
+bool forward_shape_known(const afm_plan *plan, int32_t prec, const FwdArgs &a);
 // tuned (or, under stream capture, default) shape of a plain forward launch; `launch` runs one
 // candidate on the real arguments
 hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, int nm,

@@ -569,6 +569,14 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
     return hipSuccess;
 }
 
+bool forward_shape_known(const afm_plan *plan, int32_t prec, const FwdArgs &a) {
+    if (plan->pinned_shape.block > 0) return true;
+    const int32_t has_nc = a.n_cycles != nullptr;
+    for (const FwdTune &t : plan->fwd_tune)
+        if (t.n == a.n && t.prec == prec && t.has_nc == has_nc) return true;
+    return false;
+}
+
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (prec == AFM_PREC_MIXED) return launch_law<true>(plan, a, plan->kc, s);

@@ -22,8 +22,6 @@ struct GraphCache {
     const double *targets = nullptr;
     const int32_t *ncyc = nullptr;
     const double *sparams = nullptr;
-    double *best_theta = nullptr, *best_J = nullptr;
-    int32_t *gen = nullptr;
     void *ws = nullptr;
 };
 
@@ -140,7 +138,6 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     GraphCache *g = plan->graph;
     const bool hit = g && g->S == n_swarms && g->P == particles && g->T == iters && g->seed == seed &&
                      g->cutoff == cutoff && g->targets == targets && g->ncyc == n_cycles &&
-                     g->best_theta == best_theta && g->best_J == best_J && g->gen == gen_to_cutoff &&
                      g->ws == plan->ws && g->lb_steps == lbfgs_steps && g->lb_k == kpol &&
                      g->sparams == swarm_params;
     hipError_t e;
@@ -178,7 +175,7 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         }
         a.J = J;
         a.status = status;
-        if (!n_cycles) {
+        if (!n_cycles && !forward_shape_known(plan, plan->precision, a)) {
             // the captured forward launches take whatever launch shape the plan holds for this
             // batch size, so let it be tuned first: an eager swarm init and forward, ordered
             // after the caller's earlier work (the graph repeats both)
@@ -212,7 +209,6 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
                                    lbfgs_steps, kPolishStride, Jsel, plan->stream);
             if (e == hipSuccess) e = enqueue_merge(sw, kpol, zsel, Jsel, plan->stream);
         }
-        if (e == hipSuccess) e = launch_gather_best(plan, sw, best_theta, best_J, gen_to_cutoff, plan->stream);
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(plan->stream, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -233,9 +229,6 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         g->cutoff = cutoff;
         g->targets = targets;
         g->ncyc = n_cycles;
-        g->best_theta = best_theta;
-        g->best_J = best_J;
-        g->gen = gen_to_cutoff;
         g->ws = plan->ws;
         g->lb_steps = lbfgs_steps;
         g->lb_k = kpol;
@@ -245,6 +238,10 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     e = hipEventRecord(plan->ev_in, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->stream, plan->ev_in, 0);
     if (e == hipSuccess) e = hipGraphLaunch(g->exec, plan->stream);
+    // the results go to the caller's buffers outside the graph, so that a graph is replayed
+    // whatever output buffers each call brings
+    if (e == hipSuccess)
+        e = launch_gather_best(plan, sw, best_theta, best_J, gen_to_cutoff, plan->stream);
     if (e == hipSuccess) e = hipEventRecord(plan->ev_out, plan->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, plan->ev_out, 0);
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_invert launch");

@@ -29,6 +29,9 @@ def separations(afm, model, base, pixel_free, pixel_values, setpoint, *, precisi
     m = dict(model, n_cycles=int(periods), lockin_cycles=int(lockin))
     free = [(0, 0.0, 1.0, False)] + [(int(q), 0.0, 1.0, False) for q in pixel_free]
     plan = afm.Plan(m, base, free, precision=precision, device=device)
+    # each round is one long launch of a new size: skip the launch-shape tuning (which would
+    # run it once per candidate) and take GPU-filling 4-wave workgroups
+    plan.set_launch_shape(256, 1)
 
     def amplitudes(z):  # z: [S][k] -> A [S][k]
         k = z.shape[1]
