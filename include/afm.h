@@ -145,8 +145,9 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * trajectory for 2 modes, 4 for 3 or 4; the paper's mapping of modes to threads, Sec. 3.2) --
  * times each with events and keeps the fastest; that call synchronises the stream.  Under stream
  * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,
- * else 256; one trajectory per lane).  afm_invert tunes before it captures.  Every shape
- * computes bit-identical results.
+ * else 256; one lane per mode for several modes and at most 16384 trajectories, else one
+ * trajectory per lane).  afm_invert tunes before it captures.  Every shape computes
+ * bit-identical results.
  * block in {64, 128, 256} and tpl in {1, 2, 0} (0 = one lane per mode) pin the shape for this
  * plan (a tpl that does not apply falls back to 1); block = 0 returns to tuning.  Anything
  * else: AFM_ERR_INVALID. */
@@ -176,7 +177,9 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
  * Arguments as afm_misfit; per-trajectory n_cycles must not exceed the problem's n_cycles.
  * Outputs (device): J [n], dJ [n_free][n] = dJ/dtheta_j in 1/(SI unit of parameter j), status.
  * ckpt_stride: RK4 steps between checkpoints, or 0 = autotuned (the first call with a new n
- * times the strides 16, 64 and 256 and keeps the fastest; that call synchronises the stream).
+ * times the strides 16, 64 and 256 -- with several modes each with one lane per trajectory and
+ * one lane per mode -- and keeps the fastest; that call synchronises the stream).  Every
+ * stride and form computes the same bits.
  * Workspace (checkpoints, segment buffer) is owned by the plan and grown on demand. */
 afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
                           const int32_t *target_id, const double *targets, int32_t n_targets,

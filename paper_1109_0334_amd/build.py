@@ -2,8 +2,9 @@
 
 Usage: python -m paper_1109_0334_amd.build   (or build() from Python)
 
-Every HIP translation unit is compiled with packed FP32 instructions disabled: the kernels are
-written in scalar FP32/FP64 and must not be auto-vectorised into v_pk_* forms.
+Every HIP translation unit is compiled with packed FP32 instructions disabled (the kernels are
+written in scalar FP32/FP64 and must not be auto-vectorised into v_pk_* forms) and with
+floating-point contraction limited to single expressions.
 """
 from __future__ import annotations
 
@@ -25,6 +26,11 @@ ARCH = os.environ.get("AFM_OFFLOAD_ARCH", "gfx950")
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b + c into an fma only within one source expression, the same way in every
+    # template instantiation (the default leaves the choice to the backend, which can fuse a
+    # different product of a*b + c*d in two instantiations of the same code and so break the
+    # bit-identity of launch shapes and kernel forms)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
     "-I", INCLUDE, "-I", CSRC,
 ]

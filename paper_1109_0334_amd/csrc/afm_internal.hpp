@@ -468,6 +468,7 @@ struct GradArgs {
     int32_t kc;            // checkpoint stride in RK4 steps
     const double *base;    // optional per-point full parameter vectors [kMaxParams][base_ld]
     int64_t base_ld;
+    int32_t mp;            // mode-parallel kernel (one lane per mode; several modes only)
 };
 
 // ------------------------------------------------------------------------------------------
@@ -512,6 +513,7 @@ struct afm_plan {
     size_t gws_bytes = 0;
     int64_t tuned_n = -1;
     int32_t tuned_kc = 0;
+    int32_t tuned_mp = 0;
     // plan-owned workspace for afm_polish
     void *pws = nullptr;
     size_t pws_bytes = 0;

@@ -272,12 +272,13 @@ static afm_status ensure_grad_ws(afm_plan *plan, size_t bytes) {
 }
 
 
-static afm_status run_grad(afm_plan *plan, GradArgs a, int32_t kc, hipStream_t s) {
+static afm_status run_grad(afm_plan *plan, GradArgs a, int32_t kc, int32_t mp, hipStream_t s) {
     const size_t cb = grad_ckpt_bytes(plan, plan->precision, a.n, kc);
     const size_t sb = grad_seg_bytes(plan, plan->precision, a.n, kc);
     afm_status st = ensure_grad_ws(plan, cb + ((sb + 255) & ~(size_t)255) + 256);
     if (st != AFM_OK) return st;
     a.kc = kc;
+    a.mp = plan->kc.nm > 1 ? mp : 0;
     a.seg = (float *)plan->gws;
     a.ckpt = (float *)((char *)plan->gws + ((sb + 255) & ~(size_t)255));
     hipError_t e = launch_grad(plan, a, s);
@@ -321,18 +322,27 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     a.dJ = dJ;
     a.status = status;
     hipStream_t s = (hipStream_t)stream;
-    if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, s);
-    if (plan->tuned_n == n && plan->tuned_kc > 0) return run_grad(plan, a, plan->tuned_kc, s);
-    // autotune: time each candidate stride on this call's inputs, keep the fastest
-    const int32_t cand[3] = {16, 64, 256};
+    const bool tuned = plan->tuned_n == n && plan->tuned_kc > 0;
+    // mode-parallel (several modes) unless tuning found otherwise; both compute the same bits
+    const int32_t mp_default = tuned ? plan->tuned_mp : (n * 4 <= 65536 ? 1 : 0);
+    if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, mp_default, s);
+    if (tuned) return run_grad(plan, a, plan->tuned_kc, plan->tuned_mp, s);
+    // autotune: time each candidate stride (and, with several modes, one lane per trajectory vs
+    // one lane per mode) on this call's inputs, keep the fastest
+    struct Cand { int32_t kc, mp; };
+    std::vector<Cand> cand;
+    for (int32_t kc : {16, 64, 256}) {
+        cand.push_back({kc, 0});
+        if (plan->kc.nm > 1) cand.push_back({kc, 1});
+    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(AFM_ERR_HIP, "afm_grad_batch: event creation failed");
     float best_ms = 0;
-    int32_t best = cand[1];
-    for (int c = 0; c < 3; ++c) {
+    Cand best = cand[0];
+    for (size_t c = 0; c < cand.size(); ++c) {
         (void)hipEventRecord(e0, s);
-        st = run_grad(plan, a, cand[c], s);
+        st = run_grad(plan, a, cand[c].kc, cand[c].mp, s);
         if (st != AFM_OK) break;
         (void)hipEventRecord(e1, s);
         float ms = 0;
@@ -349,7 +359,8 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     (void)hipEventDestroy(e1);
     if (st != AFM_OK) return st;
     plan->tuned_n = n;
-    plan->tuned_kc = best;
+    plan->tuned_kc = best.kc;
+    plan->tuned_mp = best.mp;
     return AFM_OK;  // the last candidate's results are in the outputs
 }
 

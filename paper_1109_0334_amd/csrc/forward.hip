@@ -533,7 +533,9 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
             *out = t.shape;
             return hipSuccess;
         }
-    FwdShape def{a.n < kSmallBatch ? 64 : 256, 1};
+    // default: one lane per mode while the groups still fit one wave per SIMD (there it
+    // shortens every wave's instruction stream); otherwise one lane per trajectory
+    FwdShape def{a.n < kSmallBatch ? 64 : 256, (nm > 1 && a.n * 4 <= kSmallBatch) ? 0 : 1};
     *out = def;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(s, &cs);

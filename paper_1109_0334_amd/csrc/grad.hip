@@ -28,9 +28,7 @@ __device__ __forceinline__ void stage_vjp(const R (&kbx)[NM], const R (&kbv)[NM]
                                           const R (&dc)[L::NC], const R (&om2)[NM],
                                           const R (&cd)[NM], R (&Ybx)[NM], R (&Ybv)[NM],
                                           R (&gsf)[L::NC], R &gzf) {
-    R S = kbv[0];
-#pragma unroll
-    for (int i = 1; i < NM; ++i) S += kbv[i];
+    const R S = mode_sum<NM>(kbv);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         Ybx[i] = Ops<R>::fma(-om2[i], kbv[i], Fd * S);
@@ -218,8 +216,8 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 const double u = sample<NM, COMP>(x, cx, zc);
                 const double U = Urow[n + 1 - first_w] * 1e9;
                 const double e = U - u;
-                Jn += e * e;
-                Jd += U * U;
+                Jn = __builtin_fma(e, e, Jn);
+                Jd = __builtin_fma(U, U, Jd);
             }
         }
         bool fin = true;
@@ -340,9 +338,289 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     A.status[i] = 0;
 }
 
+// ------------------------------------------------------------------------------------------
+// Mode-parallel adjoint: G lanes per trajectory (G = 2 for two modes, 4 for three or four),
+// lane q owning mode q in the forward pass, the checkpoints, the segment buffer and the reverse
+// sweep (the transposed stage Jacobians are per mode apart from the force terms, whose sums over
+// modes are butterfly sums over the group).  The same operations in the same order as k_grad,
+// so the same bits.  A lane without a mode carries an exact zero forward; its adjoint is left
+// out of every group sum.
+
+template <int NM, int G, class L, typename R>
+__device__ __forceinline__ void stage_eval_mp(const L &law, const ModeLane<R> &ml, R x, R v,
+                                              R D, R &a, R &Fd, R &Fdd, R (&dc)[L::NC]) {
+    const R d = group_sum<G>(x);
+    const R dd = group_sum<G>(v);
+    R F = law.grad(d, dd, Fd, Fdd, dc);
+    if constexpr (NM < G) F *= ml.w;
+    a = Ops<R>::fma(-ml.om2, x - ml.zoff, Ops<R>::fma(-ml.cd, v, Ops<R>::fma(ml.gn, D, F)));
+}
+
+template <int NM, int G, class L, typename R>
+__device__ __forceinline__ void stage_vjp_mp(const ModeLane<R> &ml, bool real, R kbx, R kbv,
+                                             R Fd, R Fdd, const R (&dc)[L::NC], R &Ybx, R &Ybv,
+                                             R (&gsf)[L::NC], R &gzf) {
+    const R S = group_sum<G>(real ? kbv : R(0));
+    Ybx = Ops<R>::fma(-ml.om2, kbv, Fd * S);
+    Ybv = Ops<R>::fma(-ml.cd, kbv, Ops<R>::fma(Fdd, S, kbx));
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) gsf[k] = Ops<R>::fma(S, dc[k], gsf[k]);
+    gzf = Ops<R>::fma(S, Fd, gzf);
+}
+
+template <int NM, int G, class L, typename R>
+__device__ __forceinline__ void reverse_step_mp(const L &law, const ModeLane<R> &ml, bool real,
+                                                R x, R v, R &xb, R &vb, R h, R h2, R h3, R h6,
+                                                R D0, R D1, R D2, R (&gsf)[L::NC], R &gzf) {
+    R a1, a2, a3, a4, Y, V2, V3, V4;
+    R Fd1, Fdd1, Fd2, Fdd2, Fd3, Fdd3, Fd4, Fdd4;
+    R dc1[L::NC], dc2[L::NC], dc3[L::NC], dc4[L::NC];
+    stage_eval_mp<NM, G>(law, ml, x, v, D0, a1, Fd1, Fdd1, dc1);
+    Y = Ops<R>::fma(h2, v, x);
+    V2 = Ops<R>::fma(h2, a1, v);
+    stage_eval_mp<NM, G>(law, ml, Y, V2, D1, a2, Fd2, Fdd2, dc2);
+    Y = Ops<R>::fma(h2, V2, x);
+    V3 = Ops<R>::fma(h2, a2, v);
+    stage_eval_mp<NM, G>(law, ml, Y, V3, D1, a3, Fd3, Fdd3, dc3);
+    Y = Ops<R>::fma(h, V3, x);
+    V4 = Ops<R>::fma(h, a3, v);
+    stage_eval_mp<NM, G>(law, ml, Y, V4, D2, a4, Fd4, Fdd4, dc4);
+    R kbx = h6 * xb, kbv = h6 * vb, Ybx, Ybv, sx, sv;
+    stage_vjp_mp<NM, G, L>(ml, real, kbx, kbv, Fd4, Fdd4, dc4, Ybx, Ybv, gsf, gzf);
+    sx = Ybx;
+    sv = Ybv;
+    kbx = Ops<R>::fma(h3, xb, h * Ybx);
+    kbv = Ops<R>::fma(h3, vb, h * Ybv);
+    stage_vjp_mp<NM, G, L>(ml, real, kbx, kbv, Fd3, Fdd3, dc3, Ybx, Ybv, gsf, gzf);
+    sx += Ybx;
+    sv += Ybv;
+    kbx = Ops<R>::fma(h3, xb, h2 * Ybx);
+    kbv = Ops<R>::fma(h3, vb, h2 * Ybv);
+    stage_vjp_mp<NM, G, L>(ml, real, kbx, kbv, Fd2, Fdd2, dc2, Ybx, Ybv, gsf, gzf);
+    sx += Ybx;
+    sv += Ybv;
+    kbx = Ops<R>::fma(h6, xb, h2 * Ybx);
+    kbv = Ops<R>::fma(h6, vb, h2 * Ybv);
+    stage_vjp_mp<NM, G, L>(ml, real, kbx, kbv, Fd1, Fdd1, dc1, Ybx, Ybv, gsf, gzf);
+    xb += sx + Ybx;
+    vb += sv + Ybv;
+}
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr bool COMP = MIXED;
+    constexpr int G = NM <= 2 ? 2 : 4;
+    constexpr int NS = 4 * NM;
+    constexpr int NB = 2 * NM + 1;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= A.n) return;  // whole groups (block size a multiple of 4)
+    const int q = threadIdx.x & (G - 1);
+    const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+    const bool real = q < NM;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const L law(p, K);
+    const double zc = p[0] * 1e9;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int N = K.N;
+    const int64_t W = (int64_t)K.lockin * N;
+    const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : 0;
+    const int kc = A.kc;
+    const int64_t n_lanes = A.n;
+    auto fail = [&](int32_t st) {
+        if (q != 0) return;
+        A.J[i] = INFINITY;
+        for (int j = 0; j < K.n_free; ++j) A.dJ[(int64_t)j * A.ld + i] = NAN;
+        A.status[i] = st;
+    };
+    if (nc < K.lockin || nc > K.n_cycles || row < 0 || row >= A.n_targets) {
+        fail(AFM_ST_BAD_INPUT);
+        return;
+    }
+    const double *__restrict__ Urow = A.targets + row * W;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+
+    ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
+    R x = R(0), v = R(0), cx = R(0), cv = R(0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        if (q == m) {
+            ml.om2 = (R)K.om2[m];
+            ml.cd = (R)K.cdamp[m];
+            ml.gn = (R)K.gain[m];
+            ml.zoff = m == 0 ? law.zc : R(0);
+            ml.w = R(1);
+            x = (R)(m == 0 ? zc + K.y0[0] : K.y0[m]);
+            v = (R)K.y0[NM + m];
+        }
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h3 = (R)(K.h / 3.0), h6 = (R)(K.h / 6.0);
+    float *__restrict__ ck = A.ckpt;
+    float *__restrict__ sg = A.seg;
+    // this lane's scalar `var` (own mode's index) of slot `slot` in a [slot][nvar][n] buffer
+    auto at = [&](int64_t slot, int var, int nvar) { return (slot * nvar + var) * n_lanes + i; };
+
+    // ---- forward pass with checkpoints
+    const int64_t Ntot = (int64_t)nc * N;
+    const int64_t first_w = Ntot - W + 1;
+    double Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+    int64_t n = 0;
+    int cdn = 0;
+    for (int c = 0; c < nc && !st; ++c) {
+        for (int s = 0; s < N; ++s, ++n) {
+            if (cdn == 0) {
+                const int64_t slot = n / kc;
+                if (real) {
+                    if constexpr (MIXED) {
+                        ck[at(slot, q, NS)] = x;
+                        ck[at(slot, NM + q, NS)] = v;
+                        ck[at(slot, 2 * NM + q, NS)] = cx;
+                        ck[at(slot, 3 * NM + q, NS)] = cv;
+                    } else {
+                        double *ckd = reinterpret_cast<double *>(ck);
+                        ckd[at(slot, q, NS)] = x;
+                        ckd[at(slot, NM + q, NS)] = v;
+                    }
+                }
+                cdn = kc;
+            }
+            --cdn;
+            rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                                             Dt[2 * s + 1], Dt[2 * s + 2]);
+            if (n + 1 >= first_w) {
+                const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
+                const double U = Urow[n + 1 - first_w] * 1e9;
+                const double e = U - u;
+                Jn = __builtin_fma(e, e, Jn);
+                Jd = __builtin_fma(U, U, Jd);
+            }
+        }
+        int nonfinite = !(isfinite(x) && isfinite(v));
+        nonfinite |= __shfl_xor(nonfinite, 1, 64);
+        if constexpr (G == 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
+        if (nonfinite) st = AFM_ST_NONFINITE;
+        else if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > K.div_nm) st = AFM_ST_DIVERGED;
+    }
+    const double J = Jn / Jd;
+    if (st || !isfinite(J)) {
+        fail(st ? st : AFM_ST_NONFINITE);
+        return;
+    }
+    const double coef = -2.0 / Jd;
+
+    // ---- reverse sweep
+    R xb = R(0), vb = R(0);
+    double gs[L::NC];
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) gs[k] = 0.0;
+    double gz = 0.0;
+    const int64_t nseg = (Ntot + kc - 1) / kc;
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int64_t n0 = sgi * kc;
+        const int64_t n1 = n0 + kc < Ntot ? n0 + kc : Ntot;
+        if (real) {
+            if constexpr (MIXED) {
+                x = ck[at(sgi, q, NS)];
+                v = ck[at(sgi, NM + q, NS)];
+                cx = ck[at(sgi, 2 * NM + q, NS)];
+                cv = ck[at(sgi, 3 * NM + q, NS)];
+            } else {
+                const double *ckd = reinterpret_cast<const double *>(ck);
+                x = ckd[at(sgi, q, NS)];
+                v = ckd[at(sgi, NM + q, NS)];
+            }
+        }
+        int s = (int)(n0 % N);
+        for (int64_t qq = n0; qq < n1; ++qq) {
+            const int64_t k = qq - n0;
+            if (real) {
+                if constexpr (MIXED) {
+                    sg[at(k, q, NB)] = x;
+                    sg[at(k, NM + q, NB)] = v;
+                } else {
+                    double *sgd = reinterpret_cast<double *>(sg);
+                    sgd[at(k, q, NB)] = x;
+                    sgd[at(k, NM + q, NB)] = v;
+                }
+            }
+            rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                                             Dt[2 * s + 1], Dt[2 * s + 2]);
+            if (qq + 1 >= first_w) {
+                const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
+                const double ub = coef * (Urow[qq + 1 - first_w] * 1e9 - u);
+                if (q == 0) {
+                    if constexpr (MIXED) sg[at(k, 2 * NM, NB)] = (R)ub;
+                    else reinterpret_cast<double *>(sg)[at(k, 2 * NM, NB)] = ub;
+                }
+            }
+            s = s + 1 == N ? 0 : s + 1;
+        }
+        s = (int)((n1 - 1) % N);
+        for (int64_t qq = n1 - 1; qq >= n0; --qq) {
+            const int64_t k = qq - n0;
+            R yx = R(0), yv = R(0);
+            if (qq + 1 >= first_w) {
+                R ub;
+                if constexpr (MIXED) ub = sg[at(k, 2 * NM, NB)];
+                else ub = reinterpret_cast<const double *>(sg)[at(k, 2 * NM, NB)];
+                if (real) xb += ub;
+            }
+            if (real) {
+                if constexpr (MIXED) {
+                    yx = sg[at(k, q, NB)];
+                    yv = sg[at(k, NM + q, NB)];
+                } else {
+                    const double *sgd = reinterpret_cast<const double *>(sg);
+                    yx = sgd[at(k, q, NB)];
+                    yv = sgd[at(k, NM + q, NB)];
+                }
+            }
+            R gsf[L::NC];
+#pragma unroll
+            for (int k2 = 0; k2 < L::NC; ++k2) gsf[k2] = R(0);
+            R gzf = R(0);
+            reverse_step_mp<NM, G, L>(law, ml, real, yx, yv, xb, vb, h, h2, h3, h6, Dt[2 * s],
+                                      Dt[2 * s + 1], Dt[2 * s + 2], gsf, gzf);
+#pragma unroll
+            for (int k2 = 0; k2 < L::NC; ++k2) gs[k2] += (double)gsf[k2];
+            gz += (double)gzf;
+            s = s == 0 ? N - 1 : s - 1;
+        }
+    }
+    if (q != 0) return;
+    double g[kMaxParams];
+#pragma unroll
+    for (int qp = 0; qp < kMaxParams; ++qp) g[qp] = 0.0;
+    L::to_si(p, K, gs, gz, g);
+    A.J[i] = J;
+    for (int j = 0; j < K.n_free; ++j) {
+        double gj = 0.0;
+#pragma unroll
+        for (int qp = 0; qp < kMaxParams; ++qp)
+            if (K.free_index[j] == qp) gj = g[qp];
+        A.dJ[(int64_t)j * A.ld + i] = gj;
+    }
+    A.status[i] = 0;
+}
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
     const int block = 64;
+    if constexpr (NM > 1) {
+        if (a.mp) {
+            constexpr int G = NM <= 2 ? 2 : 4;
+            const int64_t grid = (a.n * G + block - 1) / block;
+            hipLaunchKernelGGL((k_grad_mp<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0,
+                               s, a, K);
+            return hipGetLastError();
+        }
+    }
     const int64_t grid = (a.n + block - 1) / block;
     hipLaunchKernelGGL((k_grad<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0, s, a, K);
     return hipGetLastError();

@@ -378,6 +378,8 @@ hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
     ga.kc = kc;
     ga.base = base;
     ga.base_ld = n;
+    // one lane per mode while the groups fit one wave per SIMD (same bits, shorter streams)
+    ga.mp = plan->kc.nm > 1 && n * 4 <= 65536;
     ga.seg = (float *)((char *)ws + align256(polish_ws_bytes(n, D, L)));
     ga.ckpt = (float *)((char *)ga.seg + align256(grad_seg_bytes(plan, prec, n, kc)));
     hipError_t e = launch_grad_p(plan, prec, ga, s);

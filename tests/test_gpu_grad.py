@@ -213,3 +213,37 @@ def test_grad_fp64_other_laws(afm, orc):
         for k, i in enumerate(np.flatnonzero(ok)):
             if err[k] > PT.GRAD_TOL64:
                 assert err[k] <= PT.grad_tolerance(orc, m, P[i], U, free, fp64=True), (name, i)
+
+
+@pytest.mark.parametrize("nm", [2, 3, 4])
+def test_grad_mode_parallel_bit_identical(afm, orc, nm):
+    """The mode-parallel adjoint (one lane per mode; small batches) returns the same bits at
+    every checkpoint stride as one lane per trajectory (explicit stride above 16384 points);
+    J equals afm_misfit's."""
+    c = W.config("c5")
+    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
+    m = dict(c["model"], n_modes=nm, q=[400.0] * nm, ratio=[1.0, 6.27, 17.55, 34.39][:nm],
+             gain=gains, n_cycles=40)
+    base, free = W.full_params(c), W.free_index(c)
+    rng = np.random.default_rng(60 + nm)
+    n = 37
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), n)) if f[3] else
+                   rng.uniform(f[1], f[2], n) for f in free])
+    U = _target(orc, c, m, base)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    ref = None
+    for kc in (16, 64, 256):
+        r = [x.cpu().numpy() for x in plan.grad_batch(th, U[None, :], ckpt_stride=kc)]
+        if ref is None:
+            ref = r
+        for a, b in zip(r, ref):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), kc
+    Jm, _ = plan.misfit(th, U[None, :])
+    assert np.array_equal(ref[0], Jm.cpu().numpy())
+    # above 16384 trajectories an explicit stride runs one lane per trajectory: the same points
+    # repeated past that size must give the same bits as the mode-parallel small batch
+    big = np.tile(th, (1, 16400 // n + 1))
+    rb = [x.cpu().numpy() for x in plan.grad_batch(big, U[None, :], ckpt_stride=64)]
+    assert np.array_equal(rb[0][:n].view(np.uint8), ref[0].view(np.uint8))
+    assert np.array_equal(rb[1][:, :n].view(np.uint8), ref[1].view(np.uint8))
+    assert np.array_equal(rb[2][:n], ref[2])
