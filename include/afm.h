@@ -143,7 +143,8 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * lanes, times one trajectory per lane, two trajectories per lane (point-mass problems without
  * per-trajectory period counts) or one lane per mode (problems with several modes: 2 lanes per
  * trajectory for 2 modes, 4 for 3 or 4; the paper's mapping of modes to threads, Sec. 3.2) --
- * times each with events and keeps the fastest; that call synchronises the stream.  Under stream
+ * times each with events and keeps the default shape unless another is at least 2 % faster;
+ * that call synchronises the stream.  Under stream
  * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,
  * else 256; one lane per mode for several modes and at most 16384 trajectories, else one
  * trajectory per lane).  afm_invert tunes before it captures.  Every shape computes
