@@ -202,22 +202,29 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
 };
 
 // Lennard-Jones type: BL / d [(r0/d)^n - (r0/d)^m], BL = G eps n m / (n - m) / (k 1e-18).
-// Powers as exp2(n (log2 r0 - log2 d)); d <= 0 gives NaN.
+// Each term as one power of two: (r0/d)^n / d = exp2(n log2 r0 - (n + 1) log2 d), so the
+// force takes one log2, two exp2 and no reciprocal; d <= 0 gives NaN.
 template <typename R> struct Law<AFM_LAW_LJ, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = false;
-    R zc, BL, lr0, n, m;
+    R zc, BL, lr0, n, m, nl, ml, n1, m1;
     Law() = default;
     __device__ Law(const double *p, const KConst &K) {
+        const double l = ::log2(p[2] * 1e9);
         zc = (R)(p[0] * 1e9);
         BL = (R)(K.G * p[1] * p[3] * p[4] / (p[3] - p[4]) / (K.k * 1e-18));
-        lr0 = (R)::log2(p[2] * 1e9);
+        lr0 = (R)l;
         n = (R)p[3];
         m = (R)p[4];
+        nl = (R)(p[3] * l);
+        ml = (R)(p[4] * l);
+        n1 = (R)(-(p[3] + 1.0));
+        m1 = (R)(-(p[4] + 1.0));
     }
     template <int FM> __device__ inline R add(R d, R, R b) const {
-        const R ls = lr0 - Ops<R>::log2(d);
-        return Ops<R>::fma(BL * Ops<R>::rcp(d), Ops<R>::exp2(n * ls) - Ops<R>::exp2(m * ls), b);
+        const R ld = Ops<R>::log2(d);
+        return Ops<R>::fma(BL, Ops<R>::exp2(Ops<R>::fma(n1, ld, nl)) -
+                                   Ops<R>::exp2(Ops<R>::fma(m1, ld, ml)), b);
     }
 
     // constants c = (BL, lr0, n, m)
