@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "afm_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-MAX_MODES = 4
+MAX_MODES = 8
 MAX_PARAMS = 8
 LAW = {"dmt": 0, "lj": 1, "kv": 2, "hooke": 3, "sd": 4, "none": 5}
 LAW_PARAMS = {

@@ -27,7 +27,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAX_MODES 4
+#define ORC_MAX_MODES 8
 #define ORC_MAX_PARAMS 8
 
 /* Force laws.  Parameter vector p[] always holds the separation z_c at index 0. */

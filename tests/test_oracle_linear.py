@@ -156,3 +156,33 @@ def test_workload_linear_limit(orc):
     p = W.full_params(c, zc=1e-6)
     r = orc.forward(c["model"], p)
     assert abs(r["A"] / c["model"]["free_amplitude"] - 1) < 1e-5
+
+
+def _eight_modes(orc, **kw):
+    eb = orc.eb_modes(8, 501)
+    return _linear_model(n_modes=8, ratio=tuple(eb["ratio"]), gain=tuple(eb["gain"]),
+                         q=(400.0,) * 8, **kw)
+
+
+def test_periodic_orbit_eight_modes(orc):
+    """The paper's eight-mode beam (Sec. 3.2): the oracle returns to the exact periodic orbit of
+    the RK4 map after each period (N = 512 keeps the eighth mode inside RK4's stability
+    interval, h w_8 = 1.94)."""
+    m = _eight_modes(orc, N=512, drive_ratio=1.0)
+    a = orc.base_amplitude(m)
+    Phi, C = _rk4_affine_period(m, a)
+    ystar = np.linalg.solve(np.eye(len(C)) - Phi, C)
+    st, _, _, yend = orc.trajectory(m, [0.0], n_cycles=2, y0=ystar, n_out=1)
+    assert st == 0
+    assert np.all(np.abs(yend - ystar) < 1e-11 * _state_scale(m))
+
+
+def test_free_amplitude_closed_form_eight_modes(orc):
+    m = _eight_modes(orc, N=1024, n_cycles=30, lockin=20)
+    A_c, phi_c = _continuous_steady(m)
+    a = orc.base_amplitude(m)
+    assert abs(a * A_c / m["free_amplitude"] - 1) < 1e-13
+    r = orc.forward(m, [0.0])
+    assert r["status"] == 0
+    assert abs(r["A"] / m["free_amplitude"] - 1) < 2e-7
+    assert abs(r["phi"] - phi_c) < 2e-6
