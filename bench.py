@@ -39,7 +39,7 @@ FLOPS_PER_STEP_DMT1 = 68
 # HBM bytes per launch of that kernel from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by a
 # copy kernel of known size), valid only while the kernel sources are unchanged.
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forward_dmt1_c2_pmc.md")
-KERNEL_SOURCES = ["forward.hip", "rk4.hpp", "afm_internal.hpp"]
+KERNEL_SOURCES = ["forward_impl.hpp", "forward_dmt_mixed.hip", "rk4.hpp", "afm_internal.hpp"]
 
 
 def counted_traffic():
@@ -259,6 +259,30 @@ def plain_method_leg(afm, W, dev):
                      "rel_error_H": abs(bt[0] / truth[0] - 1),
                      "rel_error_Estar": abs(bt[1] / truth[1] - 1)}
     return res
+
+
+def paper_solver_leg(afm, W, dev):
+    """The paper's own forward-solve benchmark shape (Sec. 3.2): 960 independent solves of an
+    eight-mode Euler-Bernoulli cantilever, ~1000 RK4 steps each (here 3 drive periods x 400
+    steps, DMT tip force), one launch; tuned launch shape (one lane per mode where faster)."""
+    import torch
+
+    cfg = W.config("c2")
+    eb = W.beam_modes(8)
+    m = dict(cfg["model"], n_modes=8, q=[400.0] * 8, ratio=eb["ratio"], gain=eb["gain"],
+             steps_per_cycle=400, n_cycles=3, lockin_cycles=1)
+    free = W.free_index(cfg)
+    plan = afm.Plan(m, W.full_params(cfg), free, precision="mixed", device=dev)
+    n = 960
+    th = torch.tensor(W.draw_free(cfg, n, 8).T.copy(), device=dev)
+    plan.forward_batch(th)  # launch-shape tuning
+    ms = _event_ms(lambda: plan.forward_batch(th), reps=5)
+    steps = n * m["n_cycles"] * m["steps_per_cycle"]
+    return {"workload": "960 solves, 8-mode EB beam, 3 periods x 400 RK4 steps, DMT, mixed",
+            "ms_per_launch": ms, "trajectory_steps_per_s": steps / (ms * 1e-3),
+            "mode_steps_per_s": 8 * steps / (ms * 1e-3),
+            "paper": "960 solves of 8 modes x 1000 steps in 15.1 ms on a Quadro FX 5800 "
+                     "(6.36e7 trajectory-steps/s), context only"}
 
 
 def gradient_leg(afm, W, dev):
@@ -522,6 +546,7 @@ def main():
         line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg)
         line["time_to_inversion_pixels"] = pixel_time_to_inversion(afm, W, dev, 256, cutoff=1e-3)
         line["plain_method"] = plain_method_leg(afm, W, dev)
+        line["paper_solver_shape"] = paper_solver_leg(afm, W, dev)
         line["gradients"] = gradient_leg(afm, W, dev)
         line["three_mode"] = three_mode_leg(afm, W, dev, 2)
     if not args.no_cpu_baseline:

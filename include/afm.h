@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define AFM_MAX_MODES 4
+#define AFM_MAX_MODES 8
 #define AFM_MAX_PARAMS 8
 
 typedef void *afm_stream_t; /* a hipStream_t */
@@ -86,7 +86,7 @@ enum { AFM_ST_NONFINITE = 1, AFM_ST_DIVERGED = 2, AFM_ST_BAD_INPUT = 4 };
 
 /* Problem description, copied by value into a plan (FP: Sec. 2.2; IP search box: Sec. 3.4). */
 typedef struct afm_problem {
-    int32_t n_modes;         /* 1 (point mass) .. AFM_MAX_MODES tip-normalised modes          */
+    int32_t n_modes;         /* 1 (point mass) .. 4, or 8 (the paper's beam), tip-normalised  */
     int32_t law;             /* AFM_LAW_*                                                     */
     int32_t steps_per_cycle; /* N, RK4 steps per drive period, 4 .. 4096                      */
     int32_t n_cycles;        /* drive periods integrated (default per trajectory)             */

@@ -22,7 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafm.so")
 
-MAX_MODES = 4
+MAX_MODES = 8
 MAX_PARAMS = 8
 PREC = {"mixed": 0, "fp64": 1}
 LAW = {"dmt": 0, "lj": 1, "kv": 2, "hooke": 3, "sd": 4, "none": 5}

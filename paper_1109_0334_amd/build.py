@@ -20,7 +20,12 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libafm.so")
-SOURCES = ["api.hip", "forward.hip", "grad.hip", "lbfgs.hip", "pso.hip", "invert.hip"]
+# the forward kernels are compiled once per force law and precision, in parallel
+SOURCES = ["forward_dmt_mixed.hip", "forward_dmt_fp64.hip", "forward_kv_mixed.hip",
+           "forward_kv_fp64.hip", "forward_lj_mixed.hip", "forward_lj_fp64.hip",
+           "forward_hooke_mixed.hip", "forward_hooke_fp64.hip", "forward_sd_mixed.hip",
+           "forward_sd_fp64.hip", "forward_none_mixed.hip", "forward_none_fp64.hip",
+           "grad.hip", "api.hip", "forward.hip", "lbfgs.hip", "pso.hip", "invert.hip"]
 ARCH = os.environ.get("AFM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -59,7 +64,7 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libafm.so next to this file; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     r = subprocess.run([_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp],

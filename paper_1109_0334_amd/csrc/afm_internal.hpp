@@ -566,6 +566,13 @@ hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double 
 hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s);
 hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s);
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
+// Batches at and above this many trajectories are treated as GPU-filling (four-wave blocks,
+// per-lane branching force law); below it one wave owns a SIMD.
+constexpr int64_t kSmallBatch = 65536;
+// the forward kernels of one force law and precision (forward_impl.hpp, instantiated by the
+// forward_<law>_<precision>.hip units)
+template <int LAW, bool MIXED>
+hipError_t launch_fwd_law(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s);
 // whether the plan already holds a (tuned or pinned) shape for this plain forward launch
 bool forward_shape_known(const afm_plan *plan, int32_t prec, const FwdArgs &a);
 // tuned (or, under stream capture, default) shape of a plain forward launch; `launch` runs one

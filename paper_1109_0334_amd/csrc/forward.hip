@@ -1,511 +1,22 @@
-// forward.hip -- batched forward solve: RK4 time integration of the base-driven modal
-// cantilever, lock-in projection and window misfit, one trajectory per lane.
-//
-// The paper integrates the modal equations (Eq. 2) with explicit fourth-order Runge-Kutta
-// (Sec. 3.2) and evaluates the cost J_L2 (Eq. 5) for every particle of the swarm (Sec. 3.4).
-// Its GPU solver gave each mode its own thread and kept modal coefficients in shared memory;
-// here a whole trajectory lives in one lane's registers (state, Kahan compensation and the law's
-// constants), so the hot loop touches no memory except the drive and lock-in tables (uniform
-// scalar loads) and, inside the lock-in window, the measured trace.
-//
-// Precision: the mixed variant integrates in FP32 with a compensated (Kahan) state update, and
-// accumulates window samples, lock-in sums and misfit in FP64; the plain variant is FP64
-// throughout.  The drive phase comes from the integer step index (table lookup), never from an
-// accumulated FP32 time.
-#include "rk4.hpp"
+// forward.hip -- host side of the batched forward solve: the launch-shape tuner and the
+// dispatch over force laws and precisions.  The kernels (RK4 time integration of the
+// base-driven modal cantilever, lock-in projection and window misfit) are in forward_impl.hpp,
+// compiled once per law and precision by the forward_<law>_<precision>.hip units.
+#include "afm_internal.hpp"
 
 namespace afm {
 
 namespace {
 
-struct LaneOut {
-    double A, phi, J;
-    int32_t st;
-};
-
-// Integrate T trajectories of nc periods each in one lane and reduce them.  zc: separations in
-// nm (FP64).  Urow: measured window traces (m) or nullptr; trow: window trace outputs (m) or
-// nullptr.  With T > 1 the trajectories advance step by step side by side (independent
-// instruction streams the scheduler interleaves) and share the drive-table loads; a trajectory
-// that fails keeps being stepped (its results are discarded) until all have failed.
-template <int LAW, int NM, bool MIXED, int FM, int T>
-__device__ __forceinline__ void integrate(
-    const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
-    const double (&zc)[T], const KConst &K, int nc, const double *const (&Urow)[T],
-    double *const (&trow)[T], LaneOut (&o)[T]) {
-    using R = typename std::conditional<MIXED, float, double>::type;
-    constexpr bool COMP = MIXED;
-    const R *__restrict__ Dt;
-    if constexpr (MIXED) Dt = K.drive_f;
-    else Dt = K.drive_d;
-    const double *__restrict__ Lc = K.lock_c;
-    const double *__restrict__ Ls = K.lock_s;
-
-    R x[T][NM], v[T][NM], cx[T][NM], cv[T][NM], om2[NM], cd[NM], gn[NM];
-#pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        om2[i] = (R)K.om2[i];
-        cd[i] = (R)K.cdamp[i];
-        gn[i] = (R)K.gain[i];
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            x[t][i] = (R)(i == 0 ? zc[t] + K.y0[0] : K.y0[i]);
-            v[t][i] = (R)K.y0[NM + i];
-            cx[t][i] = R(0);
-            cv[t][i] = R(0);
-        }
-    }
-    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
-    const int N = K.N;
-    const int c_win = nc - K.lockin;
-    const double lim = K.div_nm;
-    double Sc[T], Ss[T], Jn[T], Jd[T];
-    int32_t st[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        Sc[t] = Ss[t] = Jn[t] = Jd[t] = 0.0;
-        st[t] = 0;
-    }
-
-    for (int c = 0; c < nc; ++c) {
-        if (c < c_win) {
-            // four steps per pass: their nine drive entries (stage times t, t + h/2, ..., t + 4h)
-            // come in as one block of uniform loads
-            int s = 0;
-            for (; s + 4 <= N; s += 4) {
-                // scalar loads: s is wave-uniform (readfirstlane says so where a divergent exit
-                // of the enclosing loop hides it) and the table is read-only for the kernel's
-                // lifetime (the constant address space says so where the compiler cannot prove
-                // that no store of this kernel aliases it)
-                using CR = const __attribute__((address_space(4))) R;
-                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
-                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
-                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, e0, e1, e2);
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, e2, e3, e4);
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, e4, e5, e6);
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, e6, e7, e8);
-            }
-            for (; s < N; ++s) {
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
-            }
-        } else {
-            const int w0 = (c - c_win) * N;
-            const double *__restrict__ Up[T];
-            double Un[T];
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                Up[t] = Urow[t] ? Urow[t] + w0 : nullptr;
-                Un[t] = Up[t] ? Up[t][0] : 0.0;
-            }
-            for (int s = 0; s < N; ++s) {
-                const double lc = Lc[s + 1], ls = Ls[s + 1];
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const double Uc = Un[t];
-                    if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
-                    // explicit fmas: with contraction left to the compiler, instantiations
-                    // that differ only in lanes per trajectory could round differently
-                    const double u = sample<NM, COMP>(x[t], cx[t], zc[t]);
-                    Sc[t] = __builtin_fma(u, lc, Sc[t]);
-                    Ss[t] = __builtin_fma(u, ls, Ss[t]);
-                    if (Up[t]) {
-                        const double U = Uc * 1e9;
-                        const double e = U - u;
-                        Jn[t] = __builtin_fma(e, e, Jn[t]);
-                        Jd[t] = __builtin_fma(U, U, Jd[t]);
-                    }
-                    if (trow[t]) trow[t][w0 + s] = u * 1e-9;
-                }
-            }
-        }
-        // end-of-period health check: every state entry finite and |u| within the limit
-        bool alive = false;
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            if (!st[t]) {
-                bool fin = true;
-#pragma unroll
-                for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[t][i]) && isfinite(v[t][i]);
-                if (!fin) st[t] = AFM_ST_NONFINITE;
-                else if (fabs(sample<NM, COMP>(x[t], cx[t], zc[t])) > lim) st[t] = AFM_ST_DIVERGED;
-            }
-            alive = alive || !st[t];
-        }
-        if (!alive) break;
-    }
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        o[t].st = st[t];
-        if (st[t]) {
-            o[t].A = NAN;
-            o[t].phi = NAN;
-            o[t].J = INFINITY;
-            if (trow[t])
-                for (int w = 0; w < K.lockin * N; ++w) trow[t][w] = NAN;
-        } else {
-            const double Wn = (double)K.lockin * N;
-            const double X = 2.0 * Sc[t] / Wn, Y = 2.0 * Ss[t] / Wn;
-            o[t].A = ::sqrt(__builtin_fma(X, X, Y * Y)) * 1e-9;
-            o[t].phi = ::atan2(-X, Y);
-            const double J = Urow[t] ? Jn[t] / Jd[t] : NAN;
-            o[t].J = (Urow[t] && !isfinite(J)) ? INFINITY : J;
-        }
-    }
-}
-
-// One lane's T trajectories ii[t] (those with act[t] false only keep the lane's time loop
-// company and write nothing): parameter load, bounds checks, integration, outputs.  All T
-// trajectories run nc periods.
-template <int LAW, int NM, bool MIXED, int FM, int T>
-__device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
-                                             const int64_t (&ii)[T], const bool (&act)[T],
-                                             int nc) {
-    using R = typename std::conditional<MIXED, float, double>::type;
-    const int64_t W = (int64_t)K.lockin * K.N;
-    Law<LAW, R> law[T];
-    double zc[T];
-    const double *Urow[T];
-    double *trow[T];
-    bool bad[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int64_t i = act[t] ? ii[t] : ii[0];
-        const int64_t grp = A.group > 0 ? i / A.group : i;
-        double p[kMaxParams];
-        load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
-        law[t] = Law<LAW, R>(p, K);
-        zc[t] = p[0] * 1e9;
-        Urow[t] = nullptr;
-        bad[t] = nc < K.lockin;
-        if (A.targets) {
-            const int64_t row = A.target_id ? (int64_t)A.target_id[grp]
-                                            : (A.row_by_group ? grp : 0);
-            bad[t] = bad[t] || row < 0 || row >= A.n_targets;
-            Urow[t] = bad[t] ? nullptr : A.targets + row * W;
-        }
-        trow[t] = (A.trace && act[t]) ? A.trace + i * W : nullptr;
-    }
-    bool all_bad = true;
-#pragma unroll
-    for (int t = 0; t < T; ++t) all_bad = all_bad && bad[t];
-    LaneOut o[T];
-    if (!all_bad) integrate<LAW, NM, MIXED, FM, T>(law, zc, K, nc, Urow, trow, o);
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        if (!act[t]) continue;
-        if (bad[t]) {
-            o[t].A = NAN;
-            o[t].phi = NAN;
-            o[t].J = INFINITY;
-            o[t].st = AFM_ST_BAD_INPUT;
-            if (trow[t])
-                for (int64_t w = 0; w < W; ++w) trow[t][w] = NAN;
-        }
-        const int64_t i = ii[t];
-        if (A.amp) A.amp[i] = o[t].A;
-        if (A.phase) A.phase[i] = o[t].phi;
-        if (A.J) A.J[i] = o[t].J;
-        if (A.status) A.status[i] = o[t].st;
-    }
-}
-
-// T trajectories per lane: lane l of block b owns b B T + t B + l, t < T (coalesced per t).
-// With T > 1 the period count must be the plan's (no per-trajectory counts).
-template <int LAW, int NM, bool MIXED, int FM, int T>
-__global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * T + threadIdx.x;
-    if (i0 >= A.n) return;
-    int64_t ii[T];
-    bool act[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        ii[t] = i0 + (int64_t)t * blockDim.x;
-        act[t] = ii[t] < A.n;
-    }
-    int nc = K.n_cycles;
-    if constexpr (T == 1) {
-        const int64_t grp = A.group > 0 ? i0 / A.group : i0;
-        if (A.n_cycles) nc = A.n_cycles[grp];
-    }
-    lane_forward<LAW, NM, MIXED, FM, T>(A, K, ii, act, nc);
-}
-
-// Mode-parallel forward: G lanes per trajectory (G = 2 for two modes, 4 for three or four),
-// lane q integrating mode q with the shared force (rk4_step_mp).  Same operations in the same
-// order as the one-lane kernel, so the same bits; the time loops, health checks and window
-// sums are group-uniform (every lane of a group sees the same gap, deflection and flags).
-template <int LAW, int NM, bool MIXED, int FM>
-__device__ __forceinline__ LaneOut integrate_mp(
-    const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
-    const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow, int q,
-    int gbase) {
-    using R = typename std::conditional<MIXED, float, double>::type;
-    constexpr bool COMP = MIXED;
-    constexpr int G = NM <= 2 ? 2 : 4;
-    const R *__restrict__ Dt;
-    if constexpr (MIXED) Dt = K.drive_f;
-    else Dt = K.drive_d;
-    const double *__restrict__ Lc = K.lock_c;
-    const double *__restrict__ Ls = K.lock_s;
-
-    ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
-    R x = R(0), v = R(0), cx = R(0), cv = R(0);
-#pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        if (q == i) {
-            ml.om2 = (R)K.om2[i];
-            ml.cd = (R)K.cdamp[i];
-            ml.gn = (R)K.gain[i];
-            ml.zoff = i == 0 ? law.zc : R(0);
-            ml.w = R(1);
-            x = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
-            v = (R)K.y0[NM + i];
-        }
-    }
-    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
-    const int N = K.N;
-    const int c_win = nc - K.lockin;
-    const double lim = K.div_nm;
-    double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
-    int32_t st = 0;
-
-    for (int c = 0; c < nc; ++c) {
-        if (c < c_win) {
-            int s = 0;
-            for (; s + 4 <= N; s += 4) {
-                using CR = const __attribute__((address_space(4))) R;
-                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
-                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
-                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e0, e1, e2);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e2, e3, e4);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e4, e5, e6);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e6, e7, e8);
-            }
-            for (; s < N; ++s)
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
-                                             Dt[2 * s + 1], Dt[2 * s + 2]);
-        } else {
-            const int w0 = (c - c_win) * N;
-            const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
-            double Un = Up ? Up[0] : 0.0;
-            for (int s = 0; s < N; ++s) {
-                const double Uc = Un;
-                if (Up) Un = Up[s + 1 < N ? s + 1 : s];
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
-                                             Dt[2 * s + 1], Dt[2 * s + 2]);
-                const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
-                Sc = __builtin_fma(u, Lc[s + 1], Sc);
-                Ss = __builtin_fma(u, Ls[s + 1], Ss);
-                if (Up) {
-                    const double U = Uc * 1e9;
-                    const double e = U - u;
-                    Jn = __builtin_fma(e, e, Jn);
-                    Jd = __builtin_fma(U, U, Jd);
-                }
-                if (trow && q == 0) trow[w0 + s] = u * 1e-9;
-            }
-        }
-        // end-of-period health check, combined over the group
-        int nonfinite = !(isfinite(x) && isfinite(v));
-        nonfinite |= __shfl_xor(nonfinite, 1, 64);
-        if constexpr (G == 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
-        if (nonfinite) {
-            st = AFM_ST_NONFINITE;
-            break;
-        }
-        if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > lim) {
-            st = AFM_ST_DIVERGED;
-            break;
-        }
-    }
-    LaneOut o;
-    o.st = st;
-    if (st) {
-        o.A = NAN;
-        o.phi = NAN;
-        o.J = INFINITY;
-        if (trow && q == 0)
-            for (int w = 0; w < K.lockin * N; ++w) trow[w] = NAN;
-    } else {
-        const double Wn = (double)K.lockin * N;
-        const double X = 2.0 * Sc / Wn, Y = 2.0 * Ss / Wn;
-        o.A = ::sqrt(__builtin_fma(X, X, Y * Y)) * 1e-9;
-        o.phi = ::atan2(-X, Y);
-        const double J = Urow ? Jn / Jd : NAN;
-        o.J = (Urow && !isfinite(J)) ? INFINITY : J;
-    }
-    return o;
-}
-
-// G lanes per trajectory; the block size is a multiple of 4, so groups never straddle a
-// workgroup and every lane of a group exits together.
-template <int LAW, int NM, bool MIXED, int FM>
-__global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KConst K) {
-    using R = typename std::conditional<MIXED, float, double>::type;
-    constexpr int G = NM <= 2 ? 2 : 4;
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    if (i >= A.n) return;
-    const int q = threadIdx.x & (G - 1);
-    const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
-    const int64_t grp = A.group > 0 ? i / A.group : i;
-    int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
-    double p[kMaxParams];
-    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
-    const Law<LAW, R> law(p, K);
-    const int64_t W = (int64_t)K.lockin * K.N;
-    const double *Urow = nullptr;
-    bool bad = nc < K.lockin;
-    if (A.targets) {
-        const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : (A.row_by_group ? grp : 0);
-        bad = bad || row < 0 || row >= A.n_targets;
-        Urow = bad ? nullptr : A.targets + row * W;
-    }
-    double *trow = A.trace ? A.trace + i * W : nullptr;
-    LaneOut o;
-    if (bad) {
-        o.A = NAN;
-        o.phi = NAN;
-        o.J = INFINITY;
-        o.st = AFM_ST_BAD_INPUT;
-        if (trow && q == 0)
-            for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
-    } else {
-        o = integrate_mp<LAW, NM, MIXED, FM>(law, p[0] * 1e9, K, nc, Urow, trow, q, gbase);
-    }
-    if (q == 0) {
-        if (A.amp) A.amp[i] = o.A;
-        if (A.phase) A.phase[i] = o.phi;
-        if (A.J) A.J[i] = o.J;
-        if (A.status) A.status[i] = o.st;
-    }
-}
-
-// Persistent work queue for batches of groups with uneven period counts (one pixel's swarm is
-// one group).  Each wavefront repeatedly takes the next item -- 64 lanes of one group -- from a
-// queue ordered longest first, until the queue is empty; every wave reaches the exit.  The
-// group's period count is the same for all lanes of an item, so it is moved to a scalar
-// register and the time loops run as uniform scalar loops.
-template <int LAW, int NM, bool MIXED, int FM>
-__global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KConst K) {
-    const int lane = threadIdx.x & 63;
-    for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(A.head, 1);
-        item = __shfl(item, 0, 64);
-        if (item >= A.n_items) break;
-        const int id = A.items[item];
-        const int64_t grp = id / A.chunks;
-        const int64_t local = (int64_t)(id % A.chunks) * 64 + lane;
-        int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
-        nc = __builtin_amdgcn_readfirstlane(nc);
-        if (local < A.group) {
-            const int64_t ii[1] = {grp * A.group + local};
-            const bool act[1] = {true};
-            lane_forward<LAW, NM, MIXED, FM, 1>(A, K, ii, act, nc);
-        }
-    }
-}
-
-__global__ void k_queue_reset(int32_t *head) {
-    if (threadIdx.x == 0) *head = 0;
-}
-
-// Force-law form by regime (not tuned: the per-lane branching form rounds the in-contact
-// attraction differently, and tuning must never change results).  Small batches (fewer waves
-// than SIMDs) are issue-latency bound: the branch-free form needs the fewest issue slots.  Large
-// batches are throughput bound: the per-lane branch (fewer transcendental ops; other waves
-// hide its scalar instructions).
-constexpr int64_t kSmallBatch = 65536;
-
-// Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
-template <int LAW, int NM, bool MIXED>
-hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStream_t s) {
-    constexpr bool branchy = Law<LAW, float>::kBranch;
-    const int64_t per_block = (int64_t)sh.block * sh.tpl;
-    const dim3 grid((unsigned)((a.n + per_block - 1) / per_block)), blk((unsigned)sh.block);
-    const bool large = branchy && a.n >= kSmallBatch;
-    if constexpr (NM > 1) {
-        if (sh.tpl == 0) {  // mode-parallel: G lanes per trajectory
-            constexpr int G = NM <= 2 ? 2 : 4;
-            const int64_t per = sh.block / G;
-            const dim3 g2((unsigned)((a.n + per - 1) / per));
-            if (large) hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmBranch>), g2, blk, 0, s, a, K);
-            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree>), g2, blk, 0, s, a, K);
-            return hipGetLastError();
-        }
-    }
-    if constexpr (NM == 1) {
-        if (sh.tpl == 2) {
-            if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 2>), grid, blk, 0, s, a, K);
-            else hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 2>), grid, blk, 0, s, a, K);
-            return hipGetLastError();
-        }
-    }
-    if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 1>), grid, blk, 0, s, a, K);
-    else hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1>), grid, blk, 0, s, a, K);
-    return hipGetLastError();
-}
-
-template <int LAW, int NM, bool MIXED>
-hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
-    constexpr bool branchy = Law<LAW, float>::kBranch;
-    if (a.items) {
-        // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one
-        // swarm (one separation), so they enter contact together: the wave-uniform skip form
-        // (measured 11 % faster here than the per-lane branching form)
-        hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
-        const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
-        hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree>),
-                           dim3(blocks), dim3(256), 0, s, a, K);
-        return hipGetLastError();
-    }
-    FwdShape sh;
-    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM, s,
-                                 [&](FwdShape c) { return launch_plain<LAW, NM, MIXED>(a, K, c, s); },
-                                 &sh);
-    if (e != hipSuccess) return e;
-    return launch_plain<LAW, NM, MIXED>(a, K, sh, s);
-}
-
-template <int LAW, bool MIXED>
-hipError_t launch_modes(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
-    switch (K.nm) {
-    case 1: return launch_t<LAW, 1, MIXED>(plan, a, K, s);
-    case 2: return launch_t<LAW, 2, MIXED>(plan, a, K, s);
-    case 3: return launch_t<LAW, 3, MIXED>(plan, a, K, s);
-    case 4: return launch_t<LAW, 4, MIXED>(plan, a, K, s);
-    }
-    return hipErrorInvalidValue;
-}
-
 template <bool MIXED>
 hipError_t launch_law(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     switch (K.law) {
-    case AFM_LAW_DMT: return launch_modes<AFM_LAW_DMT, MIXED>(plan, a, K, s);
-    case AFM_LAW_LJ: return launch_modes<AFM_LAW_LJ, MIXED>(plan, a, K, s);
-    case AFM_LAW_KV: return launch_modes<AFM_LAW_KV, MIXED>(plan, a, K, s);
-    case AFM_LAW_HOOKE: return launch_modes<AFM_LAW_HOOKE, MIXED>(plan, a, K, s);
-    case AFM_LAW_SD: return launch_modes<AFM_LAW_SD, MIXED>(plan, a, K, s);
-    case AFM_LAW_NONE: return launch_modes<AFM_LAW_NONE, MIXED>(plan, a, K, s);
+    case AFM_LAW_DMT: return launch_fwd_law<AFM_LAW_DMT, MIXED>(plan, a, K, s);
+    case AFM_LAW_LJ: return launch_fwd_law<AFM_LAW_LJ, MIXED>(plan, a, K, s);
+    case AFM_LAW_KV: return launch_fwd_law<AFM_LAW_KV, MIXED>(plan, a, K, s);
+    case AFM_LAW_HOOKE: return launch_fwd_law<AFM_LAW_HOOKE, MIXED>(plan, a, K, s);
+    case AFM_LAW_SD: return launch_fwd_law<AFM_LAW_SD, MIXED>(plan, a, K, s);
+    case AFM_LAW_NONE: return launch_fwd_law<AFM_LAW_NONE, MIXED>(plan, a, K, s);
     }
     return hipErrorInvalidValue;
 }

@@ -1,0 +1,5 @@
+// Forward kernels for the no tip force law, plain FP64.
+#include "forward_impl.hpp"
+
+template hipError_t afm::launch_fwd_law<AFM_LAW_NONE, false>(
+    const afm_plan *, const afm::FwdArgs &, const afm::KConst &, hipStream_t);

@@ -339,7 +339,8 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Mode-parallel adjoint: G lanes per trajectory (G = 2 for two modes, 4 for three or four),
+// Mode-parallel adjoint: G lanes per trajectory (G = 2 for two modes, 4 for three or four, 8 for
+// eight),
 // lane q owning mode q in the forward pass, the checkpoints, the segment buffer and the reverse
 // sweep (the transposed stage Jacobians are per mode apart from the force terms, whose sums over
 // modes are butterfly sums over the group).  The same operations in the same order as k_grad,
@@ -411,11 +412,11 @@ __global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K
     using R = typename std::conditional<MIXED, float, double>::type;
     using L = Law<LAW, R>;
     constexpr bool COMP = MIXED;
-    constexpr int G = NM <= 2 ? 2 : 4;
+    constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
     constexpr int NS = 4 * NM;
     constexpr int NB = 2 * NM + 1;
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-    if (i >= A.n) return;  // whole groups (block size a multiple of 4)
+    if (i >= A.n) return;  // whole groups (block size a multiple of 8)
     const int q = threadIdx.x & (G - 1);
     const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
     const bool real = q < NM;
@@ -503,7 +504,8 @@ __global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K
         }
         int nonfinite = !(isfinite(x) && isfinite(v));
         nonfinite |= __shfl_xor(nonfinite, 1, 64);
-        if constexpr (G == 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
+        if constexpr (G >= 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
+        if constexpr (G == 8) nonfinite |= __shfl_xor(nonfinite, 4, 64);
         if (nonfinite) st = AFM_ST_NONFINITE;
         else if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > K.div_nm) st = AFM_ST_DIVERGED;
     }
@@ -614,7 +616,7 @@ hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
     const int block = 64;
     if constexpr (NM > 1) {
         if (a.mp) {
-            constexpr int G = NM <= 2 ? 2 : 4;
+            constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
             const int64_t grid = (a.n * G + block - 1) / block;
             hipLaunchKernelGGL((k_grad_mp<LAW, NM, MIXED>), dim3((unsigned)grid), dim3(block), 0,
                                s, a, K);
@@ -633,6 +635,7 @@ hipError_t launch_modes(const GradArgs &a, const KConst &K, hipStream_t s) {
     case 2: return launch_t<LAW, 2, MIXED>(a, K, s);
     case 3: return launch_t<LAW, 3, MIXED>(a, K, s);
     case 4: return launch_t<LAW, 4, MIXED>(a, K, s);
+    case 8: return launch_t<LAW, 8, MIXED>(a, K, s);
     }
     return hipErrorInvalidValue;
 }

@@ -14,11 +14,13 @@ namespace afm {
 //
 // Sum over modes in the order a butterfly over the lanes of a mode-parallel group produces:
 // sequential up to three modes ((x0 + x1) + x2, the missing fourth lane adding an exact zero),
-// pairwise for four.  The one-lane and the mode-parallel kernels use this same order, so they
+// pairwise for four and eight.  The one-lane and the mode-parallel kernels use this same order, so they
 // compute identical bits.
 template <int NM, typename R>
 __device__ __forceinline__ R mode_sum(const R (&x)[NM]) {
-    if constexpr (NM == 4) {
+    if constexpr (NM == 8) {
+        return ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+    } else if constexpr (NM == 4) {
         return (x[0] + x[1]) + (x[2] + x[3]);
     } else {
         R d = x[0];
@@ -121,20 +123,25 @@ __device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM], do
 
 // ------------------------------------------------------------------------------------------
 // Mode-parallel form (the paper's own mapping of modes to threads, Sec. 3.2): the G lanes of a
-// group (G = 2 for two modes, 4 for three or four) hold one trajectory, lane q its mode q (a
+// group (G = 2 for two modes, 4 for three or four, 8 for eight) hold one trajectory, lane q its mode q (a
 // lane without a mode carries an exact zero).  The gap and gap rate are butterfly sums over the
 // group (DPP lane swaps, so the sum costs one add per butterfly level); every lane evaluates the
 // force law on the same sums and advances only its own mode.
 
 // Butterfly sum over the G lanes of a group; every lane gets the same bits.
+// DPP controls: quad_perm [1,0,3,2] swaps neighbours, quad_perm [2,3,0,1] swaps pairs,
+// row_half_mirror reverses each 8-lane half-row (after the two quad levels every lane of a quad
+// holds the quad's sum, so the mirror brings in the other quad's).
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-    // quad_perm [1,0,3,2] swaps neighbours, [2,3,0,1] swaps pairs
     float s = v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
                       0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
-    if constexpr (G == 4)
+    if constexpr (G >= 4)
         s = s + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
                     0, __builtin_bit_cast(int, s), 0x4E, 0xF, 0xF, false));
+    if constexpr (G == 8)
+        s = s + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                    0, __builtin_bit_cast(int, s), 0x141, 0xF, 0xF, false));
     return s;
 }
 
@@ -150,7 +157,8 @@ __device__ __forceinline__ double dpp_swap(double a) {
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
     double s = v + dpp_swap<0xB1>(v);
-    if constexpr (G == 4) s = s + dpp_swap<0x4E>(s);
+    if constexpr (G >= 4) s = s + dpp_swap<0x4E>(s);
+    if constexpr (G == 8) s = s + dpp_swap<0x141>(s);
     return s;
 }
 

@@ -76,7 +76,7 @@ def _base_model():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n_modes=0), dict(n_modes=5), dict(law=9), dict(steps_per_cycle=3),
+    dict(n_modes=0), dict(n_modes=9), dict(law=9), dict(steps_per_cycle=3),
     dict(steps_per_cycle=5000), dict(lockin_cycles=0), dict(n_cycles=1, lockin_cycles=2),
     dict(k=0.0), dict(free_amplitude=-1.0), dict(q=[0.0]), dict(ic=7)])
 def test_invalid_problem_rejected_before_hip(afm, bad):
@@ -110,3 +110,13 @@ def test_launch_shape_arguments_checked(afm):
     L = afm.lib()
     assert L.afm_set_launch_shape(None, 64, 1) == 1
     assert afm.lib().afm_last_error().decode()
+
+
+@pytest.mark.parametrize("nm", [5, 6, 7])
+def test_unbuilt_mode_counts_reported(afm, nm):
+    """1-4 and 8 modes are built; 5-7 are refused as unsupported (not as invalid)."""
+    m = dict(_base_model(), n_modes=nm, q=[400.0] * nm, ratio=list(range(1, nm + 1)),
+             gain=[1.0] * nm)
+    prob = afm.make_problem(m, [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9])
+    h = C.c_void_p()
+    assert afm.lib().afm_plan_create(C.byref(prob), 0, C.byref(h)) == 4 and not h.value

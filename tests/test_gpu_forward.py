@@ -326,7 +326,7 @@ def test_launch_shapes_bit_identical(afm, orc, precision, n, nc):
         assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
 
 
-@pytest.mark.parametrize("nm,law", [(2, "dmt"), (3, "kv"), (4, "kv")])
+@pytest.mark.parametrize("nm,law", [(2, "dmt"), (3, "kv"), (4, "kv"), (8, "kv")])
 def test_mode_parallel_bit_identical(afm, orc, nm, law):
     """Mode-parallel launches (one lane per mode, butterfly sums over the group) give the same
     bits as one lane per trajectory, on a ragged batch (partial workgroups); sampled points
@@ -334,9 +334,14 @@ def test_mode_parallel_bit_identical(afm, orc, nm, law):
     import torch
 
     c = W.config("c5")
-    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
-    m = dict(c["model"], law=law, n_modes=nm, q=[400.0] * nm,
-             ratio=[1.0, 6.27, 17.55, 34.39][:nm], gain=gains, n_cycles=60)
+    if nm == 8:  # the paper's eight-mode Euler-Bernoulli beam
+        eb = orc.eb_modes(8, 501)
+        ratio, gains = list(eb["ratio"]), list(eb["gain"])
+    else:
+        ratio = [1.0, 6.27, 17.55, 34.39][:nm]
+        gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
+    m = dict(c["model"], law=law, n_modes=nm, q=[400.0] * nm, ratio=ratio, gain=gains,
+             n_cycles=60)
     npar = 5 if law == "dmt" else 6
     base = W.full_params(c)[:npar]
     free = [f for f in W.free_index(c) if f[0] < npar]

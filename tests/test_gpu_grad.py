@@ -215,15 +215,19 @@ def test_grad_fp64_other_laws(afm, orc):
                 assert err[k] <= PT.grad_tolerance(orc, m, P[i], U, free, fp64=True), (name, i)
 
 
-@pytest.mark.parametrize("nm", [2, 3, 4])
+@pytest.mark.parametrize("nm", [2, 3, 4, 8])
 def test_grad_mode_parallel_bit_identical(afm, orc, nm):
     """The mode-parallel adjoint (one lane per mode; small batches) returns the same bits at
     every checkpoint stride as one lane per trajectory (explicit stride above 16384 points);
     J equals afm_misfit's."""
     c = W.config("c5")
-    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
-    m = dict(c["model"], n_modes=nm, q=[400.0] * nm, ratio=[1.0, 6.27, 17.55, 34.39][:nm],
-             gain=gains, n_cycles=40)
+    if nm == 8:
+        eb = orc.eb_modes(8, 501)
+        ratio, gains = list(eb["ratio"]), list(eb["gain"])
+    else:
+        ratio = [1.0, 6.27, 17.55, 34.39][:nm]
+        gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
+    m = dict(c["model"], n_modes=nm, q=[400.0] * nm, ratio=ratio, gain=gains, n_cycles=40)
     base, free = W.full_params(c), W.free_index(c)
     rng = np.random.default_rng(60 + nm)
     n = 37
@@ -247,3 +251,31 @@ def test_grad_mode_parallel_bit_identical(afm, orc, nm):
     assert np.array_equal(rb[0][:n].view(np.uint8), ref[0].view(np.uint8))
     assert np.array_equal(rb[1][:, :n].view(np.uint8), ref[1].view(np.uint8))
     assert np.array_equal(rb[2][:n], ref[2])
+
+
+def test_grad_eight_modes_matches_oracle_adjoint(afm, orc):
+    """The paper's eight-mode beam with the Kelvin-Voigt law: mixed adjoint against the oracle's
+    exact discrete adjoint (conditioning-aware tolerance), 6 points, 60 periods x 512 steps."""
+    c = W.config("c5")
+    eb = orc.eb_modes(8, 501)
+    m = dict(c["model"], n_modes=8, q=[400.0] * 8, ratio=list(eb["ratio"]),
+             gain=list(eb["gain"]), n_cycles=60)
+    base, free = W.full_params(c), W.free_index(c)
+    rng = np.random.default_rng(88)
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), 6)) if f[3] else
+                   rng.uniform(f[1], f[2], 6) for f in free])
+    U = _target(orc, c, m, base)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    J, dJ, st = (x.cpu().numpy() for x in plan.grad_batch(th, U[None, :]))
+    P = PT.full_from_free(base, free, th)
+    Jo, go, sto = _oracle_grads(orc, m, P, free, U)
+    zs = _zscale(free, th)
+    for i in range(6):
+        assert (st[i] != 0) == (sto[i] != 0)
+        if st[i]:
+            continue
+        assert abs(J[i] - Jo[i]) <= PT.misfit_tol(Jo[i]) or not PT.well_conditioned(orc, m, P[i])
+        e = np.linalg.norm((dJ[:, i] - go[:, i]) * zs[:, i]) / np.linalg.norm(go[:, i] * zs[:, i])
+        tol = PT.GRAD_TOL if e <= PT.GRAD_TOL else PT.grad_tolerance(orc, m, P[i], U, free)
+        print(f"8-mode point {i}: rel err {e:.2e} (tolerance {tol:.1e})")
+        assert e <= tol

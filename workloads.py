@@ -93,6 +93,11 @@ def stored_setpoints() -> dict:
         return json.load(f)
 
 
+def beam_modes(n: int) -> dict:
+    """Stored frequency ratios and base-drive gains of the first n Euler-Bernoulli modes."""
+    return stored_setpoints()[f"eb{n}"]
+
+
 def config(name: str, **overrides) -> dict:
     """A deep-enough copy of a workload with its stored z_c (and 3-mode gains) filled in."""
     c = json.loads(json.dumps(CONFIGS[name]))
