@@ -32,7 +32,9 @@
  *   - A trajectory that becomes non-finite or exceeds |u| > div_limit * A0 at the end of a drive
  *     period is not an error: its status word gets AFM_ST_NONFINITE / AFM_ST_DIVERGED, its
  *     amplitude and phase are NaN and its misfit +inf.
- *   - A plan is not thread-safe: use one plan per host thread.
+ *   - A plan is not thread-safe: use one plan per host thread.  Its workspaces (gradient
+ *     checkpoints, polish state, inversion swarms) are reused by every call, so calls on one
+ *     plan must be ordered: issue them on one stream, or synchronise between streams.
  */
 #ifndef AFM_H
 #define AFM_H

@@ -143,11 +143,20 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     hipError_t e;
     const int32_t chunks = (particles + 63) / 64;
     const int32_t n_items = n_swarms * chunks;
+    if (!hit) {
+        // a new graph rewrites the plan's workspace (queue order, tuning launches): let earlier
+        // replays on the plan's stream finish first
+        e = hipStreamSynchronize(plan->stream);
+        if (e != hipSuccess) return hip_fail(e, "afm_invert waiting for earlier replays");
+    }
     if (!hit && n_cycles) {
         // work queue: the groups' 64-lane chunks, longest period count first (read once, when
-        // the graph is built; the order only affects load balance, never the results)
+        // the graph is built; the order only affects load balance, never the results).  The
+        // counts are read on the caller's stream, after the caller's earlier work.
         std::vector<int32_t> nc(n_swarms), items(n_items);
-        e = hipMemcpy(nc.data(), n_cycles, sizeof(int32_t) * n_swarms, hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(nc.data(), n_cycles, sizeof(int32_t) * n_swarms, hipMemcpyDeviceToHost,
+                           (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "afm_invert reading n_cycles");
         std::iota(items.begin(), items.end(), 0);
         std::stable_sort(items.begin(), items.end(),
