@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "afm_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 MAX_MODES = 8
-MAX_PARAMS = 8
+MAX_PARAMS = 12
 LAW = {"dmt": 0, "lj": 1, "kv": 2, "hooke": 3, "sd": 4, "none": 5}
 LAW_PARAMS = {
     "dmt": ("zc", "H", "Estar", "a0", "R"),
@@ -42,12 +42,13 @@ class _Model(C.Structure):
         ("k", C.c_double), ("f0", C.c_double), ("drive_freq", C.c_double),
         ("free_amplitude", C.c_double), ("div_limit", C.c_double),
         ("q", C.c_double * MAX_MODES), ("ratio", C.c_double * MAX_MODES),
-        ("gain", C.c_double * MAX_MODES),
+        ("gain", C.c_double * MAX_MODES), ("drive_mode", C.c_int32),
     ]
 
 
 MODEL_FIELDS = ("n_modes", "law", "steps_per_cycle", "n_cycles", "lockin_cycles", "ic", "k", "f0",
-                "drive_freq", "free_amplitude", "div_limit", "q", "ratio", "gain")
+                "drive_freq", "free_amplitude", "div_limit", "q", "ratio", "gain", "drive_mode")
+DRIVE = {"table": 0, "params": 1}
 
 
 def build(force: bool = True) -> str:
@@ -152,7 +153,18 @@ def make_model(m: dict) -> _Model:
     gain = list(m.get("gain", [1.0] * nm))
     for i in range(nm):
         s.q[i], s.ratio[i], s.gain[i] = q[i], ratio[i], gain[i]
+    drive = m.get("drive", "table")
+    s.drive_mode = DRIVE[drive] if isinstance(drive, str) else int(drive)
     return s
+
+
+def _pv(p):
+    """Parameter vector padded to MAX_PARAMS entries (law parameters first; with the "params"
+    drive the base motion a, f, g at 8, 9, 10)."""
+    v = np.zeros(MAX_PARAMS)
+    p = np.asarray(p, dtype=np.float64).ravel()
+    v[: len(p)] = p
+    return v
 
 
 def window_len(m: dict) -> int:
@@ -176,7 +188,7 @@ def trajectory(m: dict, p, n_cycles=None, y0=None, n_out=None, want_rate=False):
     L, mo = lib(), make_model(m)
     nc = int(m["n_cycles"] if n_cycles is None else n_cycles)
     n_out = window_len(m) if n_out is None else int(n_out)
-    p = _f64(p)
+    p = _pv(p)
     u = np.empty(n_out)
     ud = np.empty(n_out) if want_rate else None
     yend = np.empty(2 * mo.n_modes)
@@ -189,7 +201,7 @@ def forward(m: dict, p, target=None, n_cycles=None, want_trace=False):
     """One forward solve: dict(status, A, phi, J, trace)."""
     L, mo = lib(), make_model(m)
     nc = int(m["n_cycles"] if n_cycles is None else n_cycles)
-    p = _f64(p)
+    p = _pv(p)
     U = None if target is None else _f64(target)
     A, phi, J = C.c_double(), C.c_double(), C.c_double()
     tr = np.empty(window_len(m)) if want_trace else None
@@ -239,12 +251,12 @@ def initial_state(m: dict):
 
 
 def force(m: dict, p, d: float, dd: float = 0.0) -> float:
-    p = _f64(p)
+    p = _pv(p)
     return lib().orc_force(law_id(m), _dp(p), float(d), float(dd))
 
 
 def steady_amplitude(m: dict, p, max_cycles=4000, rtol=1e-10):
-    p = _f64(p)
+    p = _pv(p)
     used = C.c_int32()
     mo = make_model(m)
     A = lib().orc_steady_amplitude(C.byref(mo), _dp(p), int(max_cycles), float(rtol),
@@ -253,7 +265,7 @@ def steady_amplitude(m: dict, p, max_cycles=4000, rtol=1e-10):
 
 
 def zc_from_setpoint(m: dict, p, setpoint: float, max_cycles=4000, rtol=1e-10, tol=1e-9):
-    p = _f64(p)
+    p = _pv(p)
     mo = make_model(m)
     return lib().orc_zc_from_setpoint(C.byref(mo), _dp(p), float(setpoint), int(max_cycles),
                                       float(rtol), float(tol))
@@ -263,11 +275,12 @@ def misfit_grad(m: dict, p, target, n_cycles=None):
     """(status, J, dJ/dp) with the gradient over every entry of the full parameter vector."""
     L, mo = lib(), make_model(m)
     nc = int(m["n_cycles"] if n_cycles is None else n_cycles)
-    p, U = _f64(p), _f64(target)
+    n = len(np.atleast_1d(p))
+    p, U = _pv(p), _f64(target)
     J = C.c_double()
     g = np.empty(MAX_PARAMS)
     st = L.orc_misfit_grad(C.byref(mo), _dp(p), nc, _dp(U), C.byref(J), _dp(g))
-    return st, J.value, g[: len(p)].copy()
+    return st, J.value, g[:n].copy()
 
 
 # --------------------------------------------------------------------------------------------
@@ -337,7 +350,7 @@ def pso_invert(m: dict, p_fixed, free, target, P, T, seed, cutoff=0.0, **pso):
     D = len(idx)
     bz, bJ, gen = np.empty(D), C.c_double(), C.c_int32()
     hist = np.empty(T)
-    pf, U = _f64(p_fixed), _f64(target)
+    pf, U = _pv(p_fixed), _f64(target)
     lib().orc_pso_invert(C.byref(mo), _dp(pf), D, _ip(idx), _dp(lo), _dp(hi), _ip(lg), _dp(U),
                          int(P), int(T), int(seed), float(cutoff), c["w"], c["c1"], c["c2"],
                          c["vmax"], _dp(bz), C.byref(bJ), C.byref(gen), _dp(hist))
@@ -348,7 +361,7 @@ def lbfgs(m: dict, p_fixed, free, target, z0, steps):
     mo = make_model(m)
     idx, lo, hi, lg = _free_spec(free)
     z = _f64(z0).copy()
-    pf, U = _f64(p_fixed), _f64(target)
+    pf, U = _pv(p_fixed), _f64(target)
     J = lib().orc_lbfgs(C.byref(mo), _dp(pf), len(idx), _ip(idx), _dp(lo), _dp(hi), _ip(lg),
                         _dp(U), _dp(z), int(steps))
     return z, J

@@ -28,7 +28,7 @@
 #include <string.h>
 
 #define ORC_MAX_MODES 8
-#define ORC_MAX_PARAMS 8
+#define ORC_MAX_PARAMS 12
 
 /* Force laws.  Parameter vector p[] always holds the separation z_c at index 0. */
 enum {
@@ -59,9 +59,22 @@ typedef struct {
     double q[ORC_MAX_MODES];     /* quality factor per mode                         */
     double ratio[ORC_MAX_MODES]; /* w_i / w_0                                        */
     double gain[ORC_MAX_MODES];  /* gamma_i: base-drive participation of mode i      */
+    int32_t drive_mode;          /* ORC_DRIVE_*                                      */
 } orc_model;
 
+/* Base motion.  TABLE: y_b = a sin(wd t) with a set from the free amplitude A0 (the force
+ * inversions).  PARAMS: y_b = a sin(2 pi (f t + g t^2 / 2)) with a = p[8] (m), f = p[9] (Hz) and
+ * g = p[10] (Hz/s) per trajectory, the base-motion and chirp inversions of Sec. 4; the time
+ * step stays 1 / (drive_freq N). */
+enum { ORC_DRIVE_TABLE = 0, ORC_DRIVE_PARAMS = 1 };
+enum { ORC_P_A = 8, ORC_P_F = 9, ORC_P_G = 10 };
+
 int orc_law_param_count(int law) { return (law >= 0 && law <= 5) ? orc_law_nparams[law] : -1; }
+
+/* Entries of p that describe one trajectory: the law's, plus the base motion's with PARAMS. */
+static int param_count(const orc_model *mo) {
+    return mo->drive_mode == ORC_DRIVE_PARAMS ? ORC_MAX_PARAMS : orc_law_param_count(mo->law);
+}
 
 /* ------------------------------------------------------------------------------------------ */
 /* Derived constants                                                                          */
@@ -250,7 +263,16 @@ static void rhs(const orc_model *mo, const orc_derived *dv, const double *p, dou
         ud += y[m + i];
     }
     double F = orc_force(mo->law, p, p[0] + u, ud);
-    double base_acc = dv->a * dv->wd * dv->wd * sin(dv->wd * t); /* -y_b''(t) */
+    double base_acc; /* -y_b''(t) */
+    if (mo->drive_mode == ORC_DRIVE_PARAMS) {
+        /* y_b = a sin(phi), phi = 2 pi (f t + g t^2 / 2), phi' = 2 pi (f + g t), phi'' = 2 pi g:
+         * -y_b'' = a (phi'^2 sin(phi) - phi'' cos(phi)) */
+        double a = p[ORC_P_A], f = p[ORC_P_F], g = p[ORC_P_G];
+        double phi = 2.0 * M_PI * (f * t + 0.5 * g * t * t), om = 2.0 * M_PI * (f + g * t);
+        base_acc = a * (om * om * sin(phi) - 2.0 * M_PI * g * cos(phi));
+    } else {
+        base_acc = dv->a * dv->wd * dv->wd * sin(dv->wd * t);
+    }
     for (int i = 0; i < m; i++) {
         dy[i] = y[m + i];
         dy[m + i] = -dv->w[i] * dv->w[i] * y[i] - dv->c[i] * y[m + i] + F / dv->M +
@@ -444,7 +466,7 @@ double orc_steady_amplitude(const orc_model *mo, const double *p, int32_t max_cy
  * during the search; returns z_c (NaN if no crossing down to z_c = 0). */
 double orc_zc_from_setpoint(const orc_model *mo, const double *p_in, double setpoint,
                             int32_t max_cycles, double rtol, double tol) {
-    int np = orc_law_param_count(mo->law);
+    int np = param_count(mo);
     double p[ORC_MAX_PARAMS];
     memcpy(p, p_in, sizeof(double) * np);
     double A0 = mo->free_amplitude, target = setpoint * A0;
@@ -663,6 +685,11 @@ int orc_misfit_grad(const orc_model *mo, const double *p, int32_t n_cycles, cons
     orc_derived dv;
     derive(mo, &dv);
     int m = dv.m, ns = 2 * m, np = orc_law_param_count(mo->law);
+    if (mo->drive_mode != ORC_DRIVE_TABLE) { /* the base motion's derivatives are not built */
+        for (int j = 0; j < ORC_MAX_PARAMS; j++) grad[j] = NAN;
+        *J_out = NAN;
+        return 8;
+    }
     int64_t N = mo->steps_per_cycle, Ntot = (int64_t)n_cycles * N, W = (int64_t)mo->lockin_cycles * N;
     double *ys = (double *)malloc(sizeof(double) * ns * (Ntot + 1));
     orc_initial_state(mo, ys);
@@ -753,7 +780,7 @@ void orc_pso_invert(const orc_model *mo, const double *p_fixed, int32_t n_free, 
                     int32_t P, int32_t T, uint64_t seed, double cutoff, double w, double c1,
                     double c2, double vmax, double *best_z, double *best_J, int32_t *gen,
                     double *hist) {
-    int32_t D = n_free, np = orc_law_param_count(mo->law);
+    int32_t D = n_free, np = param_count(mo);
     double *z = malloc(sizeof(double) * D * P), *v = malloc(sizeof(double) * D * P);
     double *pz = malloc(sizeof(double) * D * P), *pJ = malloc(sizeof(double) * P);
     double *J = malloc(sizeof(double) * P), gz[ORC_MAX_PARAMS], gJ;
@@ -781,7 +808,7 @@ void orc_pso_invert(const orc_model *mo, const double *p_fixed, int32_t n_free, 
 static double misfit_z(const orc_model *mo, const double *p_fixed, int32_t n_free,
                        const int32_t *idx, const double *lo, const double *hi, const int32_t *logs,
                        const double *U, const double *z, double *gz) {
-    int32_t np = orc_law_param_count(mo->law);
+    int32_t np = param_count(mo);
     double p[ORC_MAX_PARAMS], g[ORC_MAX_PARAMS], J;
     theta_from_z(p_fixed, np, n_free, idx, lo, hi, logs, z, p);
     if (gz) {
