@@ -63,9 +63,9 @@ typedef struct {
 } orc_model;
 
 /* Base motion.  TABLE: y_b = a sin(wd t) with a set from the free amplitude A0 (the force
- * inversions).  PARAMS: y_b = a sin(2 pi (f t + g t^2 / 2)) with a = p[8] (m), f = p[9] (Hz) and
- * g = p[10] (Hz/s) per trajectory, the base-motion and chirp inversions of Sec. 4; the time
- * step stays 1 / (drive_freq N). */
+ * inversions).  PARAMS: the chirp of Eq. 10, y_b = a sin(2 pi (f + g t) t), with a = p[8] (m),
+ * f = p[9] (Hz) and g = p[10] (Hz/s) per trajectory (g = 0: the sinusoid of Eq. 9), the
+ * base-motion and chirp inversions of Sec. 4; the time step stays 1 / (drive_freq N). */
 enum { ORC_DRIVE_TABLE = 0, ORC_DRIVE_PARAMS = 1 };
 enum { ORC_P_A = 8, ORC_P_F = 9, ORC_P_G = 10 };
 
@@ -265,11 +265,11 @@ static void rhs(const orc_model *mo, const orc_derived *dv, const double *p, dou
     double F = orc_force(mo->law, p, p[0] + u, ud);
     double base_acc; /* -y_b''(t) */
     if (mo->drive_mode == ORC_DRIVE_PARAMS) {
-        /* y_b = a sin(phi), phi = 2 pi (f t + g t^2 / 2), phi' = 2 pi (f + g t), phi'' = 2 pi g:
+        /* y_b = a sin(phi), phi = 2 pi (f + g t) t, phi' = 2 pi (f + 2 g t), phi'' = 4 pi g:
          * -y_b'' = a (phi'^2 sin(phi) - phi'' cos(phi)) */
         double a = p[ORC_P_A], f = p[ORC_P_F], g = p[ORC_P_G];
-        double phi = 2.0 * M_PI * (f * t + 0.5 * g * t * t), om = 2.0 * M_PI * (f + g * t);
-        base_acc = a * (om * om * sin(phi) - 2.0 * M_PI * g * cos(phi));
+        double phi = 2.0 * M_PI * (f + g * t) * t, om = 2.0 * M_PI * (f + 2.0 * g * t);
+        base_acc = a * (om * om * sin(phi) - 4.0 * M_PI * g * cos(phi));
     } else {
         base_acc = dv->a * dv->wd * dv->wd * sin(dv->wd * t);
     }

@@ -1,5 +1,6 @@
 """Pins of the oracle's parameter-driven base motion (the base-motion and chirp inversions of
-Sec. 4): y_b = a sin(2 pi (f t + g t^2 / 2)) with a, f, g per trajectory (p[8], p[9], p[10]).
+Sec. 4): the chirp of Eq. 10, y_b = a sin(2 pi (f + g t) t), with a, f, g per trajectory (p[8],
+p[9], p[10]).
 
 * with f at the nominal frequency, no chirp and a the amplitude the free amplitude sets, the
   trajectory equals the fixed-drive one (a different code path of the same motion);
@@ -64,7 +65,7 @@ def test_off_resonance_steady_state(orc, fr):
 
 def test_chirp_against_adaptive_integrator(orc):
     q, f0 = 50.0, 300e3
-    a, f, g = 0.4e-9, 280e3, 4e9  # sweeps 280 -> ~280.5 kHz over the 30 periods
+    a, f, g = 0.4e-9, 280e3, 1e9  # instantaneous f + 2 g t: 280 -> 480 kHz over the 30 periods
     m = _model(N=1024, n_cycles=30, lockin=30, q=q)
     st, u, ud, yend = orc.trajectory(m, _p(a, f, g), n_out=1, want_rate=True)
     assert st == 0
@@ -74,8 +75,8 @@ def test_chirp_against_adaptive_integrator(orc):
     # the same motion in absolute coordinates X = q + y_b, which needs only y_b and its rate:
     # X'' = -w0^2 (X - y_b) - (w0/Q) (X' - y_b'), so the base acceleration never appears
     def base(t):
-        phi = 2 * np.pi * (f * t + 0.5 * g * t * t)
-        return a * np.sin(phi), a * 2 * np.pi * (f + g * t) * np.cos(phi)
+        phi = 2 * np.pi * (f + g * t) * t
+        return a * np.sin(phi), a * 2 * np.pi * (f + 2 * g * t) * np.cos(phi)
 
     def rhs(t, y):
         yb, ybd = base(t)
@@ -85,8 +86,8 @@ def test_chirp_against_adaptive_integrator(orc):
     sol = solve_ivp(rhs, (0.0, T), [yb0, ybd0], method="DOP853", rtol=1e-12, atol=1e-24)
     ybT, ybdT = base(T)
     ref = np.array([sol.y[0, -1] - ybT, sol.y[1, -1] - ybdT])
-    # the chirp term 2 pi g cos(phi) is ~1e-2 of the base acceleration here, so a wrong sign or
-    # a missing term would show at ~1e-2 a Q; RK4 at 1024 steps per period is good to ~1e-9
+    # the chirp term 4 pi g cos(phi) is ~4e-3 of the base acceleration here, so a wrong sign or
+    # a missing term would show at ~4e-3 a Q; RK4 at 1024 steps per period is good to ~1e-9
     assert abs(yend[0] - ref[0]) < 1e-7 * a * q
     assert abs(yend[1] - ref[1]) < 1e-7 * a * q * w0
 
