@@ -98,7 +98,7 @@ def _pixel_problem(afm, W, dev, S):
     t_sep = time.perf_counter() - t0
     good = np.isfinite(zc)
     sp = np.tile(base[:, None], (1, S)).astype(np.float64)
-    sp = np.concatenate([sp, np.zeros((8 - sp.shape[0], S))], axis=0)
+    sp = np.concatenate([sp, np.zeros((afm.MAX_PARAMS - sp.shape[0], S))], axis=0)
     sp[0] = np.where(good, zc, base[0])
     sp[2] = pix["Estar"]
     ref = afm.Plan(m, base, [(0, 0.0, 1.0, 0), (2, 0.0, 1.0, 0)], precision="fp64", device=dev)

@@ -46,7 +46,7 @@ extern "C" {
 #endif
 
 #define AFM_MAX_MODES 8
-#define AFM_MAX_PARAMS 8
+#define AFM_MAX_PARAMS 12
 
 typedef void *afm_stream_t; /* a hipStream_t */
 
@@ -74,9 +74,25 @@ enum {
  *         dissipation, the spring-damper of Eq. 4 / Eq. 12 applied to a Hertzian contact).
  *   HOOKE {z_c, k_s}: -k_s d for d < 0 (Eq. 3 / Eq. 11).
  *   SD    {z_c, k_s, zeta_s}: -k_s d - zeta_s d' for d < 0 (Eq. 4 / Eq. 12).
- *   NONE  {z_c}: no tip force (the linear driven cantilever).                                  */
+ *   NONE  {z_c}: no tip force (the linear driven cantilever).  z_c only offsets the gap: use 0
+ *         (the mixed kernel carries mode 1 as the FP32 gap z_c + u, so a z_c far above the
+ *         deflection costs its precision).                                                     */
 enum { AFM_LAW_DMT = 0, AFM_LAW_LJ = 1, AFM_LAW_KV = 2, AFM_LAW_HOOKE = 3, AFM_LAW_SD = 4,
        AFM_LAW_NONE = 5 };
+
+/* Base motion.  TABLE: the sinusoid of Eq. 9 at drive_freq with the amplitude a fixed by the
+ * free amplitude A0 (the force inversions).  PARAMS: the chirp of Eq. 10 (Sec. 4.1),
+ * y_b = a sin(2 pi (f + g t) t), with a (m), f (Hz) and g (Hz/s) in params[8], params[9] and
+ * params[10] of each trajectory, so that they can be free parameters (the paper's base-motion
+ * inversions; g = 0 is Eq. 9).  The RHS then carries -y_b'' = a (w^2 sin(phi) - 4 pi g cos(phi)),
+ * phi = 2 pi (f + g t) t, w = 2 pi (f + 2 g t), evaluated per lane at every RK4 stage time
+ * (FP64 phase reduced to one revolution, sine and cosine in the plan's precision); the time step
+ * stays 1 / (drive_freq N) and the lock-in projects onto drive_freq.  PARAMS requires
+ * ic = AFM_IC_REST (the free steady state of a chirp is not defined).  Not built for PARAMS: the
+ * adjoint (afm_grad_batch, afm_polish and the invert polish return AFM_ERR_UNSUPPORTED) and the
+ * one-lane-per-mode and two-per-lane shapes (PARAMS always runs one trajectory per lane). */
+enum { AFM_DRIVE_TABLE = 0, AFM_DRIVE_PARAMS = 1 };
+enum { AFM_P_BASE_A = 8, AFM_P_BASE_F = 9, AFM_P_BASE_G = 10 };
 
 /* Initial state: FREE_STEADY = linear free steady state at t = 0 (q_i = Im(a H_i),
  * q_i' = wd Re(a H_i), H_i = gamma_i wd^2 / (w_i^2 - wd^2 + i w_i wd / Q_i)); REST = zero. */
@@ -97,20 +113,24 @@ typedef struct afm_problem {
     double k;                /* first-mode stiffness, N/m                                     */
     double f0;               /* first-mode natural frequency, Hz                              */
     double drive_freq;       /* base drive frequency, Hz                                      */
-    double free_amplitude;   /* A0, m; fixes the base amplitude                               */
+    double free_amplitude;   /* A0, m; fixes the base amplitude (TABLE), scales div_limit     */
     double div_limit;        /* divergence threshold in units of A0 (0 => 100)                */
     double q[AFM_MAX_MODES];     /* quality factor per mode                                   */
     double ratio[AFM_MAX_MODES]; /* w_i / w_0 (ratio[0] is normally 1)                        */
     double gain[AFM_MAX_MODES];  /* gamma_i, base-drive participation (1 for a point mass)    */
-    double params[AFM_MAX_PARAMS];      /* full law parameter vector, SI; free entries are
-                                           overwritten per trajectory by theta               */
-    int32_t n_free;                     /* D: free parameters, 1 .. AFM_MAX_PARAMS            */
-    int32_t free_index[AFM_MAX_PARAMS]; /* params[] slot of free parameter j                  */
+    double params[AFM_MAX_PARAMS];      /* full parameter vector, SI: the law's (slots 0 ..
+                                           its count - 1), with PARAMS the base motion's in
+                                           slots 8 .. 10; free entries are overwritten per
+                                           trajectory by theta; other slots ignored          */
+    int32_t n_free;                     /* D: free parameters, 0 .. law count (+ 3 with PARAMS) */
+    int32_t free_index[AFM_MAX_PARAMS]; /* params[] slot of free parameter j (a law slot, or
+                                           8 .. 10 with PARAMS)                              */
     double lo[AFM_MAX_PARAMS];          /* search box of free parameter j (SI)                */
     double hi[AFM_MAX_PARAMS];
     int32_t log_scale[AFM_MAX_PARAMS];  /* 1: theta = lo (hi/lo)^z, else lo + z (hi - lo)      */
     double pso_w, pso_c1, pso_c2, pso_vmax; /* Eq. 8 weights; 0 => 0.7298, 1.49618, 1.49618, 1 */
     int32_t polish_precision; /* arithmetic of afm_polish and the invert polish: AFM_POLISH_*   */
+    int32_t drive_mode;       /* AFM_DRIVE_* (0 = TABLE)                                       */
 } afm_problem;
 
 /* Polish arithmetic: the plan's own precision, or FP32 (mixed) / FP64 adjoint and misfits. */

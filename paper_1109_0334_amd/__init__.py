@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libafm.so")
 
 MAX_MODES = 8
-MAX_PARAMS = 8
+MAX_PARAMS = 12
 PREC = {"mixed": 0, "fp64": 1}
 LAW = {"dmt": 0, "lj": 1, "kv": 2, "hooke": 3, "sd": 4, "none": 5}
 LAW_PARAMS = {
@@ -35,6 +35,8 @@ LAW_PARAMS = {
     "none": ("zc",),
 }
 IC = {"free_steady": 0, "rest": 1}
+DRIVE = {"table": 0, "params": 1}
+P_BASE_A, P_BASE_F, P_BASE_G = 8, 9, 10  # base-motion slots of a "params" drive
 POLISH = {"plan": 0, "mixed": 1, "fp64": 2}
 ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
@@ -59,7 +61,7 @@ class _Problem(C.Structure):
         ("free_index", C.c_int32 * MAX_PARAMS), ("lo", C.c_double * MAX_PARAMS),
         ("hi", C.c_double * MAX_PARAMS), ("log_scale", C.c_int32 * MAX_PARAMS),
         ("pso_w", C.c_double), ("pso_c1", C.c_double), ("pso_c2", C.c_double),
-        ("pso_vmax", C.c_double), ("polish_precision", C.c_int32),
+        ("pso_vmax", C.c_double), ("polish_precision", C.c_int32), ("drive_mode", C.c_int32),
     ]
 
 
@@ -110,13 +112,16 @@ def _check(code: int, what: str):
 
 
 def make_problem(model: dict, params, free=(), pso=None, polish="plan") -> _Problem:
-    """afm_problem from a model dict (SI; keys as in ``workloads``), the full law parameter vector
-    and the free-parameter spec [(index, lo, hi, log_scale), ...]."""
+    """afm_problem from a model dict (SI; keys as in ``workloads``; ``drive`` "table" or
+    "params"), the full parameter vector (the law's, and with a "params" drive the base motion's
+    a, f, g at slots 8, 9, 10) and the free-parameter spec [(index, lo, hi, log_scale), ...]."""
     p = _Problem()
     law = model["law"]
     p.law = LAW[law] if isinstance(law, str) else int(law)
     ic = model.get("ic", "free_steady")
     p.ic = IC[ic] if isinstance(ic, str) else int(ic)
+    drive = model.get("drive", "table")
+    p.drive_mode = DRIVE[drive] if isinstance(drive, str) else int(drive)
     p.n_modes = int(model.get("n_modes", 1))
     p.steps_per_cycle = int(model["steps_per_cycle"])
     p.n_cycles = int(model["n_cycles"])

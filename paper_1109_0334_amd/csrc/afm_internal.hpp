@@ -36,10 +36,12 @@ struct KConst {
     int32_t n_cycles;      // default periods per trajectory
     int32_t lockin;        // lock-in periods
     int32_t n_free;        // free parameters
+    int32_t drive_mode;    // AFM_DRIVE_*
     int32_t free_index[kMaxParams];
     double params[kMaxParams];  // full SI parameter vector (free slots overwritten per lane)
     double k;              // first-mode stiffness, N/m
     double wd;             // drive angular frequency, rad/s
+    double fref;           // drive frequency, Hz (the time unit of a parameter-driven base)
     double G;              // (w0 / wd)^2
     double h;              // 2 pi / N
     double div_nm;         // divergence threshold on |u|, nm

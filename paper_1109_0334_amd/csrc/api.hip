@@ -62,10 +62,18 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     for (int i = 0; i < pr.n_modes; ++i)
         if (!(pr.q[i] > 0) || !(pr.ratio[i] > 0) || !std::isfinite(pr.gain[i]))
             return fail(AFM_ERR_INVALID, "mode quality factors and ratios must be positive");
+    if (pr.drive_mode != AFM_DRIVE_TABLE && pr.drive_mode != AFM_DRIVE_PARAMS)
+        return fail(AFM_ERR_INVALID, "unknown drive_mode");
+    const bool dparams = pr.drive_mode == AFM_DRIVE_PARAMS;
+    if (dparams && pr.ic != AFM_IC_REST)
+        return fail(AFM_ERR_INVALID, "a parameter-driven base motion needs ic = AFM_IC_REST");
     const int np = kLawParams[pr.law];
-    if (pr.n_free < 0 || pr.n_free > np) return fail(AFM_ERR_INVALID, "n_free out of range for the law");
+    // a slot a trajectory reads: the law's, and with PARAMS the base motion's (8 .. 10)
+    auto used = [&](int q) { return (q >= 0 && q < np) || (dparams && q >= AFM_P_BASE_A && q <= AFM_P_BASE_G); };
+    if (pr.n_free < 0 || pr.n_free > np + (dparams ? 3 : 0))
+        return fail(AFM_ERR_INVALID, "n_free out of range for the law");
     for (int j = 0; j < pr.n_free; ++j) {
-        if (pr.free_index[j] < 0 || pr.free_index[j] >= np)
+        if (!used(pr.free_index[j]))
             return fail(AFM_ERR_INVALID, "free_index out of range for the law");
         for (int l = 0; l < j; ++l)
             if (pr.free_index[l] == pr.free_index[j]) return fail(AFM_ERR_INVALID, "free_index repeated");
@@ -81,9 +89,11 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     K.n_cycles = pr.n_cycles;
     K.lockin = pr.lockin_cycles;
     K.n_free = pr.n_free;
+    K.drive_mode = pr.drive_mode;
+    K.fref = pr.drive_freq;
     for (int j = 0; j < kMaxParams; ++j) {
         K.free_index[j] = j < pr.n_free ? pr.free_index[j] : -1;
-        K.params[j] = j < np ? pr.params[j] : 0.0;
+        K.params[j] = used(j) ? pr.params[j] : 0.0;
     }
     K.k = pr.k;
     K.wd = 2.0 * M_PI * pr.drive_freq;
@@ -311,6 +321,8 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
         return fail(AFM_ERR_INVALID, "targets, J, dJ and status are required");
     if (n > 0 && n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");
     if (ckpt_stride < 0) return fail(AFM_ERR_INVALID, "ckpt_stride < 0");
+    if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
+        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
     if (n == 0) return AFM_OK;
     GradArgs a{};
     a.n = n;
@@ -372,6 +384,8 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     if (n < 0 || steps < 0) return fail(AFM_ERR_INVALID, "n and steps must be >= 0");
     if (plan->prob.n_free < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
+    if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
+        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
     if (n == 0) return AFM_OK;
     if (!z || !targets || !J) return fail(AFM_ERR_INVALID, "z, targets and J are required");
     if (n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");

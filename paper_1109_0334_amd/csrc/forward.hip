@@ -91,7 +91,8 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
 }
 
 bool forward_shape_known(const afm_plan *plan, int32_t prec, const FwdArgs &a) {
-    if (plan->pinned_shape.block > 0) return true;
+    // a parameter-driven base has one fixed shape
+    if (plan->pinned_shape.block > 0 || plan->kc.drive_mode != AFM_DRIVE_TABLE) return true;
     const int32_t has_nc = a.n_cycles != nullptr;
     for (const FwdTune &t : plan->fwd_tune)
         if (t.n == a.n && t.prec == prec && t.has_nc == has_nc) return true;

@@ -29,18 +29,55 @@ struct LaneOut {
     int32_t st;
 };
 
+// Base motion from a trajectory's own parameters: the chirp of Eq. 10 (g = 0 gives Eq. 9), with
+// a, f, g in parameter slots 8, 9, 10.  at(j) is the drive term -y_b'' / wd^2 in nm at half-step
+// j (time j h / 2, i.e. s = j / (2 N) drive periods): phase in revolutions rho = s (r0 + gam s),
+// rate w = r0 + 2 gam s in units of wd, term amp (w^2 sin(2 pi rho) - (gam / pi) cos(2 pi rho)),
+// r0 = f / f_d, gam = g / f_d^2.  The phase is formed and reduced to [-1/2, 1/2] in FP64 (it
+// reaches thousands of revolutions), the sine and cosine are taken in R.
+template <typename R>
+struct DriveP {
+    double c1 = 0, c2 = 0, c3 = 0, r0 = 0;  // rho = j (c1 + j c2), w = r0 + j c3
+    R amp = R(0), kg = R(0);
+    DriveP() = default;
+    __device__ DriveP(const double (&p)[kMaxParams], const KConst &K, int nm) {
+        const double inv2n = 1.0 / (2.0 * K.N);
+        const double gam = p[AFM_P_BASE_G] / (K.fref * K.fref);
+        r0 = p[AFM_P_BASE_F] / K.fref;
+        c1 = r0 * inv2n;
+        c2 = gam * inv2n * inv2n;
+        c3 = 2.0 * gam * inv2n;
+        // a point mass carries its gain in the drive term (as the fixed drive table does)
+        amp = (R)(p[AFM_P_BASE_A] * 1e9 * (nm == 1 ? K.gain[0] : 1.0));
+        kg = (R)(gam / M_PI);
+    }
+    __device__ __forceinline__ R at(double j) const {
+        const double rho = j * __builtin_fma(j, c2, c1);
+        const double r = rho - __builtin_rint(rho);
+        const R w = (R)__builtin_fma(j, c3, r0);
+        R sn, cs;
+        if constexpr (std::is_same<R, float>::value) sincospif(2.0f * (float)r, &sn, &cs);
+        else sincospi(2.0 * r, &sn, &cs);
+        return amp * Ops<R>::fma(w * w, sn, -(kg * cs));
+    }
+};
+
 // Integrate T trajectories of nc periods each in one lane and reduce them.  zc: separations in
 // nm (FP64).  Urow: measured window traces (m) or nullptr; trow: window trace outputs (m) or
 // nullptr.  With T > 1 the trajectories advance step by step side by side (independent
 // instruction streams the scheduler interleaves) and share the drive-table loads; a trajectory
-// that fails keeps being stepped (its results are discarded) until all have failed.
-template <int LAW, int NM, bool MIXED, int FM, int T>
+// that fails keeps being stepped (its results are discarded) until all have failed.  DP: the
+// drive comes from the trajectory's own base-motion parameters (dv) instead of the table (one
+// trajectory per lane).
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP>
 __device__ __forceinline__ void integrate(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
     const double (&zc)[T], const KConst &K, int nc, const double *const (&Urow)[T],
-    double *const (&trow)[T], LaneOut (&o)[T]) {
+    double *const (&trow)[T], const DriveP<typename std::conditional<MIXED, float, double>::type> &dv,
+    LaneOut (&o)[T]) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
+    static_assert(!DP || T == 1, "a parameter-driven base runs one trajectory per lane");
     const R *__restrict__ Dt;
     if constexpr (MIXED) Dt = K.drive_f;
     else Dt = K.drive_d;
@@ -72,9 +109,20 @@ __device__ __forceinline__ void integrate(
         Sc[t] = Ss[t] = Jn[t] = Jd[t] = 0.0;
         st[t] = 0;
     }
+    R Dc = R(0);  // DP: drive term at the start of the next step
+    if constexpr (DP) Dc = dv.at(0.0);
 
     for (int c = 0; c < nc; ++c) {
-        if (c < c_win) {
+        if (DP && c < c_win) {
+            const double jb = 2.0 * ((double)c * N);
+            for (int s = 0; s < N; ++s) {
+                const double j = jb + 2.0 * s;
+                const R D1 = dv.at(j + 1.0), D2 = dv.at(j + 2.0);
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       Dc, D1, D2);
+                Dc = D2;
+            }
+        } else if (c < c_win) {
             // four steps per pass: their nine drive entries (stage times t, t + h/2, ..., t + 4h)
             // come in as one block of uniform loads
             int s = 0;
@@ -119,14 +167,26 @@ __device__ __forceinline__ void integrate(
                 Up[t] = Urow[t] ? Urow[t] + w0 : nullptr;
                 Un[t] = Up[t] ? Up[t][0] : 0.0;
             }
+            const double jb = 2.0 * ((double)c * N);
             for (int s = 0; s < N; ++s) {
                 const double lc = Lc[s + 1], ls = Ls[s + 1];
+                R D0, D1, D2;
+                if constexpr (DP) {
+                    D0 = Dc;
+                    D1 = dv.at(jb + 2.0 * s + 1.0);
+                    D2 = dv.at(jb + 2.0 * s + 2.0);
+                    Dc = D2;
+                } else {
+                    D0 = Dt[2 * s];
+                    D1 = Dt[2 * s + 1];
+                    D2 = Dt[2 * s + 2];
+                }
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     const double Uc = Un[t];
                     if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
                     rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
+                                           h6, D0, D1, D2);
                     // explicit fmas: with contraction left to the compiler, instantiations
                     // that differ only in lanes per trajectory could round differently
                     const double u = sample<NM, COMP>(x[t], cx[t], zc[t]);
@@ -180,12 +240,13 @@ __device__ __forceinline__ void integrate(
 // One lane's T trajectories ii[t] (those with act[t] false only keep the lane's time loop
 // company and write nothing): parameter load, bounds checks, integration, outputs.  All T
 // trajectories run nc periods.
-template <int LAW, int NM, bool MIXED, int FM, int T>
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP>
 __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
                                              const int64_t (&ii)[T], const bool (&act)[T],
                                              int nc) {
     using R = typename std::conditional<MIXED, float, double>::type;
     const int64_t W = (int64_t)K.lockin * K.N;
+    DriveP<R> dv;
     Law<LAW, R> law[T];
     double zc[T];
     const double *Urow[T];
@@ -198,6 +259,7 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
         double p[kMaxParams];
         load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
         law[t] = Law<LAW, R>(p, K);
+        if constexpr (DP) dv = DriveP<R>(p, K, NM);
         zc[t] = p[0] * 1e9;
         Urow[t] = nullptr;
         bad[t] = nc < K.lockin;
@@ -213,7 +275,7 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
 #pragma unroll
     for (int t = 0; t < T; ++t) all_bad = all_bad && bad[t];
     LaneOut o[T];
-    if (!all_bad) integrate<LAW, NM, MIXED, FM, T>(law, zc, K, nc, Urow, trow, o);
+    if (!all_bad) integrate<LAW, NM, MIXED, FM, T, DP>(law, zc, K, nc, Urow, trow, dv, o);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         if (!act[t]) continue;
@@ -234,8 +296,9 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
 }
 
 // T trajectories per lane: lane l of block b owns b B T + t B + l, t < T (coalesced per t).
-// With T > 1 the period count must be the plan's (no per-trajectory counts).
-template <int LAW, int NM, bool MIXED, int FM, int T>
+// With T > 1 the period count must be the plan's (no per-trajectory counts).  DP: the
+// parameter-driven base motion (T = 1).
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP = false>
 __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * T + threadIdx.x;
     if (i0 >= A.n) return;
@@ -251,7 +314,7 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
         const int64_t grp = A.group > 0 ? i0 / A.group : i0;
         if (A.n_cycles) nc = A.n_cycles[grp];
     }
-    lane_forward<LAW, NM, MIXED, FM, T>(A, K, ii, act, nc);
+    lane_forward<LAW, NM, MIXED, FM, T, DP>(A, K, ii, act, nc);
 }
 
 // Mode-parallel forward: G lanes per trajectory (G = 2 for two modes, 4 for three or four, 8 for
@@ -428,7 +491,7 @@ __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KC
         if (local < A.group) {
             const int64_t ii[1] = {grp * A.group + local};
             const bool act[1] = {true};
-            lane_forward<LAW, NM, MIXED, FM, 1>(A, K, ii, act, nc);
+            lane_forward<LAW, NM, MIXED, FM, 1, false>(A, K, ii, act, nc);
         }
     }
 }
@@ -475,6 +538,15 @@ hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStrea
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
+    if (K.drive_mode != AFM_DRIVE_TABLE) {
+        // parameter-driven base: one trajectory per lane with its own drive, the branch-free law
+        // form; a work-queue batch runs as a plain grid (per-group period counts are read per
+        // lane)
+        const int block = a.n < kSmallBatch ? 64 : 256;
+        hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1, true>),
+                           dim3((unsigned)((a.n + block - 1) / block)), dim3(block), 0, s, a, K);
+        return hipGetLastError();
+    }
     if (a.items) {
         // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one
         // swarm (one separation), so they enter contact together: the wave-uniform skip form

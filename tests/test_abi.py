@@ -7,6 +7,7 @@ import re
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -44,10 +45,11 @@ _LAYOUT_PROBE = r"""
 #include <stdio.h>
 #include "afm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
          offsetof(afm_problem, params), offsetof(afm_problem, n_free),
          offsetof(afm_problem, lo), offsetof(afm_problem, pso_w),
-         offsetof(afm_problem, polish_precision), sizeof(afm_swarm));
+         offsetof(afm_problem, polish_precision), offsetof(afm_problem, drive_mode),
+         sizeof(afm_swarm));
   printf("%zu %zu\n", offsetof(afm_swarm, z), offsetof(afm_swarm, theta));
   return 0;
 }
@@ -65,7 +67,8 @@ def test_binding_struct_layout_matches_header(afm, tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P, S = afm._Problem, afm._Swarm
     expect = [C.sizeof(P), P.k.offset, P.params.offset, P.n_free.offset, P.lo.offset,
-              P.pso_w.offset, P.polish_precision.offset, C.sizeof(S), S.z.offset, S.theta.offset]
+              P.pso_w.offset, P.polish_precision.offset, P.drive_mode.offset, C.sizeof(S),
+              S.z.offset, S.theta.offset]
     assert [int(x) for x in out] == expect
 
 
@@ -78,7 +81,8 @@ def _base_model():
 @pytest.mark.parametrize("bad", [
     dict(n_modes=0), dict(n_modes=9), dict(law=9), dict(steps_per_cycle=3),
     dict(steps_per_cycle=5000), dict(lockin_cycles=0), dict(n_cycles=1, lockin_cycles=2),
-    dict(k=0.0), dict(free_amplitude=-1.0), dict(q=[0.0]), dict(ic=7)])
+    dict(k=0.0), dict(free_amplitude=-1.0), dict(q=[0.0]), dict(ic=7), dict(drive=3),
+    dict(drive="params")])  # a parameter-driven base needs ic = rest
 def test_invalid_problem_rejected_before_hip(afm, bad):
     m = dict(_base_model(), **bad)
     prob = afm.make_problem(m, [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9], [(1, 1e-20, 1e-19, 0)])
@@ -89,11 +93,25 @@ def test_invalid_problem_rejected_before_hip(afm, bad):
 
 
 @pytest.mark.parametrize("free", [
-    [(7, 0.0, 1.0, 0)], [(1, 1.0, 0.5, 0)], [(1, 0.0, 1.0, 1)], [(1, 0, 1, 0), (1, 0, 2, 0)]])
+    [(7, 0.0, 1.0, 0)], [(1, 1.0, 0.5, 0)], [(1, 0.0, 1.0, 1)], [(1, 0, 1, 0), (1, 0, 2, 0)],
+    [(9, 1e3, 2e3, 0)]])  # base-motion slots are parameters only with a "params" drive
 def test_invalid_search_box_rejected(afm, free):
     prob = afm.make_problem(_base_model(), [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9], free)
     h = C.c_void_p()
     assert afm.lib().afm_plan_create(C.byref(prob), 0, C.byref(h)) == 1
+
+
+@pytest.mark.parametrize("free", [[(11, 0.0, 1.0, 0)], [(5, 0.0, 1.0, 0)],
+                                  [(8, 0, 1e-9, 0), (8, 0, 2e-9, 0)]])
+def test_invalid_base_motion_parameters_rejected(afm, free):
+    """With a "params" drive the free slots are the law's and 8 .. 10 (a, f, g) only."""
+    m = dict(_base_model(), drive="params", ic="rest")
+    p = np.zeros(12)
+    p[:5] = [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9]
+    p[8:11] = [1e-9, 300e3, 0.0]
+    prob = afm.make_problem(m, p, free)
+    h = C.c_void_p()
+    assert afm.lib().afm_plan_create(C.byref(prob), 0, C.byref(h)) == 1 and not h.value
 
 
 def test_bad_precision_and_null_arguments(afm):

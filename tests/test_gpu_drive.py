@@ -1,0 +1,252 @@
+"""GPU forward solves and inversions with the base motion as per-trajectory parameters (the chirp
+of Eq. 10, y_b = a sin(2 pi (f + g t) t), a, f, g in parameter slots 8, 9, 10; Sec. 4.1),
+against the oracle.
+
+* forward: amplitude, phase, misfit and the window trace of point-mass, 3-mode and 8-mode
+  cantilevers, with and without a tip force, started at rest; mixed to the mixed-precision
+  tolerances of parity.py (conditioning filter for the contact cases), FP64 to 1e-9;
+* the sinusoid at the table's own frequency and amplitude reproduces the fixed-drive path;
+* inversions of the paper's base-motion problems (App. A beam, 1000 steps of 4e-8 s from rest):
+  with the FP64 forward the swarm follows the oracle swarm step for step (1-D amplitude, 3-D
+  chirp, and per-swarm period counts); the mixed forward recovers the 2-D truth;
+* the adjoint of these parameters is not built: gradients and polish report unsupported."""
+import numpy as np
+import pytest
+
+import parity as PT
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def afm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1109_0334_amd as afm
+
+    afm.lib()
+    return afm
+
+
+def _pm_model(law="none", N=256, n_cycles=30, lockin=10):
+    return dict(n_modes=1, law=law, k=40.0, f0=300e3, drive_freq=300e3, q=[400.0], ratio=[1.0],
+                gain=[1.0], free_amplitude=20e-9, steps_per_cycle=N, n_cycles=n_cycles,
+                lockin_cycles=lockin, ic="rest", div_limit=100.0, drive="params")
+
+
+def _beam_model(nm, N=1000, n_cycles=1, lockin=1, law="none"):
+    """The paper's base-motion problems: the App. A cantilever (8 Euler-Bernoulli modes, first
+    at 25468.9 Hz, k = 3 E I / L^3 = 1.33 N/m), time step 1 / (25 kHz x 1000) = 4e-8 s."""
+    eb = W.beam_modes(8) if nm == 8 else W.config("c5")["model"]  # 8 or 3 modes
+    return dict(n_modes=nm, law=law, k=1.33, f0=25468.9, drive_freq=25e3, q=[400.0] * nm,
+                ratio=list(eb["ratio"]), gain=list(eb["gain"]), free_amplitude=20e-9,
+                steps_per_cycle=N, n_cycles=n_cycles, lockin_cycles=lockin, ic="rest",
+                div_limit=1e4, drive="params")
+
+
+def _full(law_params, a, f, g):
+    p = np.zeros(12)
+    p[: len(law_params)] = law_params
+    p[8], p[9], p[10] = a, f, g
+    return p
+
+
+_DMT = [8e-9, 6.4e-20, 1.0e9, 0.3e-9, 10e-9]  # z_c, H, E*, a0, R: contact once |u| > ~8 nm
+_FREE_AFG = [(8, 0.0, 0.2e-9, 0), (9, 250e3, 350e3, 0), (10, -2e9, 2e9, 0)]
+
+
+def _draw_afg(n, seed, box=_FREE_AFG):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(lo, hi, n) for _, lo, hi, _ in box])
+
+
+def _check_forward(afm, orc, m, law_params, free, th, prec, tag):
+    import torch
+
+    P = PT.full_from_free(_full(law_params, 0.0, 0.0, 0.0), free, th)
+    U = orc.forward(m, P[0], want_trace=True)["trace"] * 0.9  # a target near the first point
+    plan = afm.Plan(m, P[0], free, precision=prec)
+    r = plan.forward_batch(torch.tensor(th, device="cuda"), trace=True)
+    J, stJ = (x.cpu().numpy() for x in plan.misfit(th, U[None, :]))
+    A, phi, st = (r[k].cpu().numpy() for k in ("amp", "phase", "status"))
+    tr = r["trace"].cpu().numpy()
+    assert np.array_equal(st, stJ)
+    n = th.shape[1]
+    o = PT.oracle_batch(orc, m, P, target=U)
+    if prec == "fp64":
+        assert np.array_equal(st != 0, o["status"] != 0)
+        ok = st == 0
+        np.testing.assert_allclose(A[ok], o["A"][ok], rtol=PT.FP64_RTOL)
+        assert np.all(np.abs(PT.wrap(phi[ok] - o["phi"][ok])) <= 1e-9)
+        np.testing.assert_allclose(J[ok], o["J"][ok], rtol=1e-9)
+        for i in np.flatnonzero(ok)[:4]:
+            to = orc.forward(m, P[i], want_trace=True)["trace"]
+            assert np.max(np.abs(tr[i] - to)) <= 1e-9 * np.max(np.abs(to)), (tag, i)
+        print(f"{tag}: {n} points, FP64 max |dA|/A "
+              f"{np.max(np.abs(A[ok] / o['A'][ok] - 1)):.2e}")
+        return
+    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, J=J, tag=tag)
+    assert not failing, failing
+    assert len(excluded) <= n // 4, excluded
+    for i in [k for k in range(min(n, 4)) if st[k] == 0 and k not in excluded]:
+        to = orc.forward(m, P[i], want_trace=True)["trace"]
+        e = np.max(np.abs(tr[i] - to)) / np.max(np.abs(to))
+        assert e <= 1e-5, (tag, i, e)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("law", ["none", "dmt"])
+def test_point_mass_chirp_forward(afm, orc, prec, law):
+    m = _pm_model(law=law)
+    th = _draw_afg(203, 1 if law == "none" else 2)  # several workgroups and a ragged tail
+    _check_forward(afm, orc, m, _DMT if law == "dmt" else [8e-9], _FREE_AFG, th, prec,
+                   f"point mass {law} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("nm,law", [(3, "kv"), (8, "none")])
+def test_beam_chirp_forward(afm, orc, prec, nm, law):
+    if nm == 8:
+        m = _beam_model(8, N=1000, n_cycles=2, lockin=2)
+        box = [(8, 0.0, 100e-9, 0), (9, 7500.0, 27000.0, 0), (10, 1.9e7, 2.1e7, 0)]
+        lawp = [0.0]  # free tip: the gap is the deflection
+    else:
+        c5 = W.config("c5")["model"]
+        m = dict(_pm_model(law="kv", N=256, n_cycles=20, lockin=5), n_modes=3,
+                 q=[400.0] * 3, ratio=list(c5["ratio"]), gain=list(c5["gain"]))
+        box = _FREE_AFG
+        lawp = _DMT + [10.0]
+    th = _draw_afg(70, 3 + nm, box)
+    _check_forward(afm, orc, m, lawp, box, th, prec, f"{nm}-mode {law} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_sinusoid_reproduces_fixed_drive(afm, orc, prec):
+    """f = drive frequency, g = 0 and a = the table's base amplitude: the per-lane drive and the
+    drive table describe the same motion, so the results agree to the precision's rounding."""
+    import torch
+
+    m_tab = dict(_pm_model(law="dmt", n_cycles=60, lockin=10), drive="table")
+    a = orc.base_amplitude(m_tab)
+    zcs = np.linspace(4e-9, 30e-9, 64)
+    free_t = [(0, 0.0, 40e-9, 0)]
+    tab = afm.Plan(m_tab, _DMT, free_t, precision=prec)
+    par = afm.Plan(_pm_model(law="dmt", n_cycles=60, lockin=10),
+                   _full(_DMT, a, 300e3, 0.0), free_t, precision=prec)
+    r0 = tab.forward_batch(torch.tensor(zcs[None, :], device="cuda"), trace=True)
+    r1 = par.forward_batch(torch.tensor(zcs[None, :], device="cuda"), trace=True)
+    st0, st1 = r0["status"].cpu().numpy(), r1["status"].cpu().numpy()
+    assert np.array_equal(st0, st1)
+    t0, t1 = r0["trace"].cpu().numpy(), r1["trace"].cpu().numpy()
+    tol = 1e-11 if prec == "fp64" else 3e-6
+    ok = st0 == 0
+    e = np.max(np.abs(t1[ok] - t0[ok]), axis=1) / np.max(np.abs(t0[ok]), axis=1)
+    well = np.array([PT.well_conditioned(orc, m_tab, np.r_[z, _DMT[1:]]) for z in zcs[ok]])
+    print(f"{prec}: max relative trace difference {e.max():.2e} (well-conditioned "
+          f"{e[well].max():.2e})")
+    assert np.all(e[well] <= tol)
+
+
+def _invert_vs_oracle(afm, orc, m, base, free, truth, P, T, seed, cutoff):
+    U = orc.forward(m, truth, want_trace=True)["trace"]
+    plan = afm.Plan(m, base, free, precision="fp64")
+    out = plan.invert(U[None, :], P, T, seed=seed, cutoff=cutoff)
+    ores = orc.pso_invert(m, base, free, U, P, T, seed, cutoff=cutoff)
+    bt = out["best_theta"].cpu().numpy()[:, 0]
+    zt = [orc.z_to_theta(ores["z"][j], *free[j][1:]) for j in range(len(free))]
+    np.testing.assert_allclose(bt, zt, rtol=1e-12)
+    assert abs(out["best_J"].item() - ores["J"]) <= 1e-9 * ores["J"] + 1e-15
+    assert out["gen_to_cutoff"].item() == ores["gen_to_cutoff"]
+    return bt, ores
+
+
+def test_invert_base_amplitude_fp64_matches_oracle(afm, orc):
+    """The paper's 1-D problem (Sec. 4.1): a in [0, 100] nm, f = 25.6 kHz fixed, truth 2 nm."""
+    m = _beam_model(8)
+    truth = _full([0.0], 2e-9, 25600.0, 0.0)
+    bt, ores = _invert_vs_oracle(afm, orc, m, truth, [(8, 0.0, 100e-9, 0)], truth, 32, 6, 21,
+                                 1e-2)
+    print(f"1-D: a = {bt[0]:.6e}, J = {ores['J']:.3e}, gen_to_cutoff {ores['gen_to_cutoff']}")
+
+
+def test_invert_chirp_fp64_matches_oracle(afm, orc):
+    """The paper's 3-D chirp problem (Sec. 4.1): truth (2 nm, 10 kHz, 2e7 Hz/s) in
+    [0, 100] nm x [7.5, 12.5] kHz x [1.9e7, 2.1e7] Hz/s."""
+    m = _beam_model(8)
+    truth = _full([0.0], 2e-9, 10e3, 2e7)
+    free = [(8, 0.0, 100e-9, 0), (9, 7500.0, 12500.0, 0), (10, 1.9e7, 2.1e7, 0)]
+    _invert_vs_oracle(afm, orc, m, truth, free, truth, 24, 4, 5, 1e-3)
+
+
+def test_invert_uneven_cycles_fp64_matches_oracle(afm, orc):
+    """Per-swarm period counts and base vectors with a parameter-driven base (the batch the
+    work queue takes with a fixed drive runs here as a plain grid): every swarm follows the
+    oracle's."""
+    m = _beam_model(3, N=200, n_cycles=3, lockin=1)
+    free = [(8, 0.0, 100e-9, 0), (9, 20e3, 30e3, 0)]
+    S, P, T, seed = 3, 40, 4, 13
+    cyc = np.array([3, 1, 2], np.int32)
+    sp = np.zeros((afm.MAX_PARAMS, S))
+    sp[0] = 0.0
+    sp[10] = [0.0, 1e7, -5e6]  # each pixel its own (fixed) chirp rate
+    U = np.stack([orc.forward(dict(m, n_cycles=int(cyc[s])), _full([0.0], 3e-9, 25.3e3,
+                                                                  sp[10, s]),
+                              want_trace=True)["trace"] for s in range(S)])
+    plan = afm.Plan(m, sp[:, 0], free, precision="fp64")
+    out = plan.invert(U, P, T, seed=seed, cutoff=1e-2, n_cycles=cyc, swarm_params=sp)
+    bt, bJ = out["best_theta"].cpu().numpy(), out["best_J"].cpu().numpy()
+    sw = orc.Swarm(len(free), P, S, seed)
+    for t in range(T):
+        J = np.empty(S * P)
+        for s in range(S):
+            ms = dict(m, n_cycles=int(cyc[s]))
+            for p in range(P):
+                q = sp[:, s].copy()
+                for j, f in enumerate(free):
+                    q[f[0]] = orc.z_to_theta(sw.z[j, s * P + p], *f[1:])
+                J[s * P + p] = orc.forward(ms, q, U[s])["J"]
+        sw.update(J, t, t == T - 1, cutoff=1e-2)
+    for s in range(S):
+        zt = [orc.z_to_theta(sw.gbest_z[j, s], *free[j][1:]) for j in range(len(free))]
+        np.testing.assert_allclose(bt[:, s], zt, rtol=1e-12)
+        assert abs(bJ[s] - sw.gbest_J[s]) <= 1e-9 * sw.gbest_J[s] + 1e-15
+
+
+def test_invert_two_parameter_mixed_recovers_truth(afm, orc):
+    """The paper's 2-D problem (a and f unknown, a 1000 Hz box): the mixed path lands on the
+    truth, and its best misfit is the oracle's at that point."""
+    m = _beam_model(8)
+    truth = _full([0.0], 2e-9, 25600.0, 0.0)
+    free = [(8, 0.0, 100e-9, 0), (9, 25100.0, 26100.0, 0)]
+    U = orc.forward(m, truth, want_trace=True)["trace"]
+    plan = afm.Plan(m, truth, free, precision="mixed")
+    out = plan.invert(U[None, :], 256, 40, seed=2, cutoff=1e-4)
+    bt = out["best_theta"].cpu().numpy()[:, 0]
+    p = truth.copy()
+    p[8], p[9] = bt
+    Jo = orc.forward(m, p, U)["J"]
+    Jg = out["best_J"].item()
+    print(f"2-D: a = {bt[0]:.6e}, f = {bt[1]:.3f}, J gpu {Jg:.3e} oracle {Jo:.3e}, "
+          f"gen_to_cutoff {out['gen_to_cutoff'].item()}")
+    assert abs(Jg - Jo) <= PT.misfit_tol(Jo)
+    assert abs(bt[0] / 2e-9 - 1) < 1e-3 and abs(bt[1] / 25600.0 - 1) < 1e-4
+
+
+def test_adjoint_reports_unsupported(afm):
+    import torch
+
+    m = _pm_model(n_cycles=4, lockin=2)
+    plan = afm.Plan(m, _full([8e-9], 0.05e-9, 300e3, 0.0), _FREE_AFG[:2], precision="mixed")
+    th = torch.tensor([[0.05e-9], [300e3]], dtype=torch.float64, device="cuda")
+    U = torch.zeros(1, plan.W, dtype=torch.float64, device="cuda") + 1e-9
+    with pytest.raises(afm.AfmError, match="status 4"):
+        plan.grad_batch(th, U)
+    with pytest.raises(afm.AfmError, match="status 4"):
+        plan.polish(torch.full((2, 1), 0.5, dtype=torch.float64, device="cuda"), U, steps=2)
+    with pytest.raises(afm.AfmError, match="status 4"):
+        plan.invert(U, 8, 2, seed=1, lbfgs_steps=2, lbfgs_topk=2)
+    out = plan.invert(U, 8, 2, seed=1)  # without the polish the inversion runs
+    assert out["best_J"].shape == (1,)

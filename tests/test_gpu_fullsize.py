@@ -45,7 +45,7 @@ def test_c3_full_size_queue_sampled(afm, orc):
     rng = np.random.default_rng(77)
     A0 = m["free_amplitude"]
     base = W.full_params(c)
-    sp = np.zeros((8, S))
+    sp = np.zeros((afm.MAX_PARAMS, S))
     sp[: len(base)] = base[:, None]
     sp[0] = pix["setpoint"] * A0 + rng.uniform(-0.5e-9, 0.5e-9, S)  # separations near the set-point
     sp[2] = pix["Estar"]

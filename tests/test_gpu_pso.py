@@ -146,7 +146,7 @@ def test_invert_uneven_queue_matches_oracle(afm, orc):
     zcs = [14.6e-9, 15.0e-9, 14.2e-9]
     estar = [1.0e9, 2.5e9, 0.6e9]
     base = W.full_params(c)
-    sp = np.zeros((8, S))
+    sp = np.zeros((afm.MAX_PARAMS, S))
     for s in range(S):
         sp[:5, s] = base
         sp[0, s], sp[2, s] = zcs[s], estar[s]
