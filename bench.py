@@ -354,6 +354,50 @@ def three_mode_leg(afm, W, dev, gens):
             "projected_s_lbfgs_10_steps": pol * cfg["lbfgs_steps"]}
 
 
+def base_motion_leg(afm, W, dev, swarms=64, particles=512, gens=40):
+    """The paper's base-motion inversions (Sec. 4.1) on its 8-mode beam: for each problem,
+    `swarms` independent swarms of `particles` on one target (one graph launch; the swarms draw
+    independent random streams) give the mean and variance of the generations to the cut-off,
+    and a single swarm gives one inversion's time per generation.  Target: the plain FP64 GPU
+    trace at the truth; inversion with the mixed forward."""
+    import torch
+
+    res = {}
+    for case in W.BASE_MOTION:
+        c = W.base_motion(case)
+        m, cut = c["model"], c["cutoff"]
+        ref = afm.Plan(m, c["params"], [], precision="fp64", device=dev)
+        U = ref.forward_batch(None, trace=True)["trace"].contiguous()
+        plan = afm.Plan(m, c["params"], c["free"], precision="mixed", device=dev)
+        Us = U.expand(swarms, -1).contiguous()
+        plan.invert(Us, particles, gens, seed=7, cutoff=cut)  # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan.invert(Us, particles, gens, seed=7, cutoff=cut)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        gen = out["gen_to_cutoff"].cpu().numpy()
+        ng = gen[gen >= 0] + 1.0  # generations evaluated up to and including the cut-off one
+        plan.invert(U, particles, gens, seed=7, cutoff=cut)  # capture (one swarm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.invert(U, particles, gens, seed=7, cutoff=cut)
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - t0) / gens * 1e3
+        mean = float(ng.mean()) if ng.size else None
+        res[case] = {
+            "free": [f[0] for f in c["free"]], "cutoff_sqrtJ": cut, "swarms": swarms,
+            "particles": particles, "generations_run": gens, "converged_swarms": int(ng.size),
+            "mean_generations_to_cutoff": mean,
+            "var_generations_to_cutoff": float(ng.var()) if ng.size else None,
+            "batch_ms_per_generation": dt / gens * 1e3,
+            "single_inversion_ms_per_generation": ms1,
+            "single_inversion_ms_to_cutoff": mean * ms1 if mean else None,
+            "paper": c["paper"]}
+    return {"workload": "App. A beam, 8 modes, 1000 RK4 steps of 4e-8 s from rest, base motion "
+                        "(a, f, g) unknown, mixed", "cases": res}
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -549,6 +593,7 @@ def main():
         line["paper_solver_shape"] = paper_solver_leg(afm, W, dev)
         line["gradients"] = gradient_leg(afm, W, dev)
         line["three_mode"] = three_mode_leg(afm, W, dev, 2)
+        line["base_motion"] = base_motion_leg(afm, W, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     line["paper_context"] = PAPER_CONTEXT

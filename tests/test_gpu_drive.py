@@ -37,14 +37,14 @@ def _pm_model(law="none", N=256, n_cycles=30, lockin=10):
                 lockin_cycles=lockin, ic="rest", div_limit=100.0, drive="params")
 
 
-def _beam_model(nm, N=1000, n_cycles=1, lockin=1, law="none"):
-    """The paper's base-motion problems: the App. A cantilever (8 Euler-Bernoulli modes, first
-    at 25468.9 Hz, k = 3 E I / L^3 = 1.33 N/m), time step 1 / (25 kHz x 1000) = 4e-8 s."""
-    eb = W.beam_modes(8) if nm == 8 else W.config("c5")["model"]  # 8 or 3 modes
-    return dict(n_modes=nm, law=law, k=1.33, f0=25468.9, drive_freq=25e3, q=[400.0] * nm,
-                ratio=list(eb["ratio"]), gain=list(eb["gain"]), free_amplitude=20e-9,
-                steps_per_cycle=N, n_cycles=n_cycles, lockin_cycles=lockin, ic="rest",
-                div_limit=1e4, drive="params")
+def _beam_model(nm, N=1000, n_cycles=1, lockin=1):
+    """The cantilever of the paper's base-motion problems (App. A beam, 8 modes, 1000 steps of
+    4e-8 s from rest, free tip), or its first three modes with c5's ratios and gains."""
+    m = W.base_motion("1d")["model"]
+    if nm == 3:
+        c5 = W.config("c5")["model"]
+        m = dict(m, n_modes=3, q=[400.0] * 3, ratio=list(c5["ratio"]), gain=list(c5["gain"]))
+    return dict(m, steps_per_cycle=N, n_cycles=n_cycles, lockin_cycles=lockin)
 
 
 def _full(law_params, a, f, g):
@@ -165,20 +165,17 @@ def _invert_vs_oracle(afm, orc, m, base, free, truth, P, T, seed, cutoff):
 
 def test_invert_base_amplitude_fp64_matches_oracle(afm, orc):
     """The paper's 1-D problem (Sec. 4.1): a in [0, 100] nm, f = 25.6 kHz fixed, truth 2 nm."""
-    m = _beam_model(8)
-    truth = _full([0.0], 2e-9, 25600.0, 0.0)
-    bt, ores = _invert_vs_oracle(afm, orc, m, truth, [(8, 0.0, 100e-9, 0)], truth, 32, 6, 21,
-                                 1e-2)
+    c = W.base_motion("1d")
+    bt, ores = _invert_vs_oracle(afm, orc, c["model"], c["params"], c["free"], c["params"], 32,
+                                 6, 21, c["cutoff"])
     print(f"1-D: a = {bt[0]:.6e}, J = {ores['J']:.3e}, gen_to_cutoff {ores['gen_to_cutoff']}")
 
 
 def test_invert_chirp_fp64_matches_oracle(afm, orc):
     """The paper's 3-D chirp problem (Sec. 4.1): truth (2 nm, 10 kHz, 2e7 Hz/s) in
     [0, 100] nm x [7.5, 12.5] kHz x [1.9e7, 2.1e7] Hz/s."""
-    m = _beam_model(8)
-    truth = _full([0.0], 2e-9, 10e3, 2e7)
-    free = [(8, 0.0, 100e-9, 0), (9, 7500.0, 12500.0, 0), (10, 1.9e7, 2.1e7, 0)]
-    _invert_vs_oracle(afm, orc, m, truth, free, truth, 24, 4, 5, 1e-3)
+    c = W.base_motion("3d_chirp")
+    _invert_vs_oracle(afm, orc, c["model"], c["params"], c["free"], c["params"], 24, 4, 5, 1e-3)
 
 
 def test_invert_uneven_cycles_fp64_matches_oracle(afm, orc):
@@ -218,9 +215,8 @@ def test_invert_uneven_cycles_fp64_matches_oracle(afm, orc):
 def test_invert_two_parameter_mixed_recovers_truth(afm, orc):
     """The paper's 2-D problem (a and f unknown, a 1000 Hz box): the mixed path lands on the
     truth, and its best misfit is the oracle's at that point."""
-    m = _beam_model(8)
-    truth = _full([0.0], 2e-9, 25600.0, 0.0)
-    free = [(8, 0.0, 100e-9, 0), (9, 25100.0, 26100.0, 0)]
+    c = W.base_motion("2d")
+    m, truth, free = c["model"], c["params"], c["free"]
     U = orc.forward(m, truth, want_trace=True)["trace"]
     plan = afm.Plan(m, truth, free, precision="mixed")
     out = plan.invert(U[None, :], 256, 40, seed=2, cutoff=1e-4)

@@ -15,6 +15,8 @@ the paper lists as its extension (adhesion / van der Waals, Sec. 5):
 * ``c4`` LJ-type law, 4 parameters, 2048 points for the adjoint gradient, 1000 x 256 steps.
 * ``c5`` 3-mode beam, Kelvin-Voigt contact + vdW, 5 parameters, 16384 x 300, 2000 x 512 steps.
 
+``base_motion`` describes the paper's base-motion inversions (Sec. 4.1) on its 8-mode beam.
+
 Separations z_c are *not* computed here: they follow from the set-point by the method's own
 amplitude feedback and are stored in ``tests/golden/setpoint_zc.json`` by a script that calls
 the oracle only.  Law parameter vectors hold z_c at index 0.
@@ -85,6 +87,45 @@ CONFIGS = {
         particles=16384, iters=300, seed=0, noise=0.0, precision="mixed", lbfgs_steps=10,
         lbfgs_topk=64),
 }
+
+
+# The paper's base-motion inversions (Sec. 4.1): the App. A cantilever -- 8 Euler-Bernoulli
+# modes, first at 25468.9 Hz, L = 525 um, E = 1.76e11 Pa, section 35 x 5 um, so
+# k = 3 E I / L^3 with I = w h^3 / 12 -- started at rest with no tip force (a free tip, z_c = 0),
+# n_t = 1000 RK4 steps of 4e-8 s (one period of a 25 kHz time unit), misfit over all of them.
+# The base motion y_b = a sin(2 pi (f + g t) t) (Eq. 9 with g = 0, Eq. 10) is the unknown.  The
+# paper gives no damping for this beam; Q = 400 per mode (one period from rest barely feels it).
+# The paper states 512 particles for the 1-D runs; the others use the same.
+_EB_I = 35e-6 * 5e-6**3 / 12.0
+_BEAM = dict(n_modes=8, law="none", k=3.0 * 1.76e11 * _EB_I / 525e-6**3, f0=25468.9,
+             drive_freq=25e3, q=[400.0] * 8, free_amplitude=20 * NM, ic="rest", div_limit=1e4,
+             steps_per_cycle=1000, n_cycles=1, lockin_cycles=1, drive="params")
+
+BASE_MOTION = {
+    "1d": dict(truth=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)], cutoff=1e-2,
+               paper=dict(generations=3.0, ms=48.0, note="mean, 512 particles, cut-off 0.01")),
+    "1d_tight": dict(truth=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)],
+                     cutoff=1e-3, paper=dict(generations=7.99, ms=128.0, note="cut-off 0.001")),
+    "2d": dict(truth=(2 * NM, 25600.0, 0.0),
+               free=[(8, 0.0, 100 * NM, False), (9, 25100.0, 26100.0, False)], cutoff=1e-2,
+               paper=dict(generations=19.0458, ms=320.0, note="a and f, a 1000 Hz box")),
+    "3d_chirp": dict(truth=(2 * NM, 10e3, 2e7),
+                     free=[(8, 0.0, 100 * NM, False), (9, 7500.0, 12500.0, False),
+                           (10, 1.9e7, 2.1e7, False)], cutoff=1e-2,
+                     paper=dict(generations=14.9, ms=240.0, note="a, f, g (chirp)")),
+}
+
+
+def base_motion(case: str) -> dict:
+    """One of the paper's base-motion problems: model, full 12-entry parameter vector at the
+    truth (law slot 0 = z_c = 0; a, f, g at 8, 9, 10), free-parameter spec, cut-off."""
+    c = BASE_MOTION[case]
+    eb = beam_modes(8)
+    model = dict(_BEAM, ratio=list(eb["ratio"]), gain=list(eb["gain"]))
+    p = np.zeros(12)
+    p[8], p[9], p[10] = c["truth"]
+    return dict(model=model, params=p, free=[tuple(f) for f in c["free"]], cutoff=c["cutoff"],
+                paper=dict(c["paper"]))
 
 
 def stored_setpoints() -> dict:
