@@ -88,9 +88,10 @@ enum { AFM_LAW_DMT = 0, AFM_LAW_LJ = 1, AFM_LAW_KV = 2, AFM_LAW_HOOKE = 3, AFM_L
  * phi = 2 pi (f + g t) t, w = 2 pi (f + 2 g t), evaluated per lane at every RK4 stage time
  * (FP64 phase reduced to one revolution, sine and cosine in the plan's precision); the time step
  * stays 1 / (drive_freq N) and the lock-in projects onto drive_freq.  PARAMS requires
- * ic = AFM_IC_REST (the free steady state of a chirp is not defined).  Not built for PARAMS: the
- * adjoint (afm_grad_batch, afm_polish and the invert polish return AFM_ERR_UNSUPPORTED) and the
- * one-lane-per-mode and two-per-lane shapes (PARAMS always runs one trajectory per lane). */
+ * ic = AFM_IC_REST (the free steady state of a chirp is not defined).  Launch shapes as for
+ * TABLE (afm_set_launch_shape) without two trajectories per lane; with one lane per mode the
+ * lanes of a trajectory split its drive evaluations between them.  Not built for PARAMS: the
+ * adjoint (afm_grad_batch, afm_polish and the invert polish return AFM_ERR_UNSUPPORTED). */
 enum { AFM_DRIVE_TABLE = 0, AFM_DRIVE_PARAMS = 1 };
 enum { AFM_P_BASE_A = 8, AFM_P_BASE_F = 9, AFM_P_BASE_G = 10 };
 
@@ -159,12 +160,14 @@ afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_pl
 afm_status afm_plan_destroy(afm_plan *plan);
 
 /* Launch shape of the plain forward kernel (afm_forward_batch, afm_misfit, the swarm
- * evaluations of afm_invert without per-swarm period counts, polish line searches).  By default
+ * evaluations of afm_invert without per-swarm period counts -- with them too for a
+ * parameter-driven base --, polish line searches).  By default
  * (block = 0) it is autotuned per precision, batch size and period-count mode: the first call
  * with a new combination runs the launch once per candidate -- workgroups of 64, 128 or 256
- * lanes, times one trajectory per lane, two trajectories per lane (point-mass problems without
- * per-trajectory period counts) or one lane per mode (problems with several modes: 2 lanes per
- * trajectory for 2 modes, 4 for 3 or 4; the paper's mapping of modes to threads, Sec. 3.2) --
+ * lanes, times one trajectory per lane, two trajectories per lane (point-mass problems with the
+ * fixed drive and without per-trajectory period counts) or one lane per mode (problems with
+ * several modes: 2 lanes per trajectory for 2 modes, 4 for 3 or 4, 8 for 8; the paper's mapping
+ * of modes to threads, Sec. 3.2) --
  * times each with events and keeps the default shape unless another is at least 2 % faster;
  * that call synchronises the stream.  Under stream
  * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,

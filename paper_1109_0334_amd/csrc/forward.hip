@@ -33,7 +33,7 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
                          hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
                          FwdShape *out) {
     const int32_t has_nc = a.n_cycles != nullptr;
-    const bool pair_ok = nm == 1 && !has_nc;
+    const bool pair_ok = nm == 1 && !has_nc && plan->kc.drive_mode == AFM_DRIVE_TABLE;
     if (plan->pinned_shape.block > 0) {
         *out = plan->pinned_shape;
         if ((out->tpl == 2 && !pair_ok) || (out->tpl == 0 && nm == 1)) out->tpl = 1;
@@ -91,8 +91,7 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
 }
 
 bool forward_shape_known(const afm_plan *plan, int32_t prec, const FwdArgs &a) {
-    // a parameter-driven base has one fixed shape
-    if (plan->pinned_shape.block > 0 || plan->kc.drive_mode != AFM_DRIVE_TABLE) return true;
+    if (plan->pinned_shape.block > 0) return true;
     const int32_t has_nc = a.n_cycles != nullptr;
     for (const FwdTune &t : plan->fwd_tune)
         if (t.n == a.n && t.prec == prec && t.has_nc == has_nc) return true;

@@ -321,12 +321,13 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
 // eight),
 // lane q integrating mode q with the shared force (rk4_step_mp).  Same operations in the same
 // order as the one-lane kernel, so the same bits; the time loops, health checks and window
-// sums are group-uniform (every lane of a group sees the same gap, deflection and flags).
-template <int LAW, int NM, bool MIXED, int FM>
+// sums are group-uniform (every lane of a group sees the same gap, deflection and flags).  DP:
+// the parameter-driven base, every lane of the group evaluating the same drive terms.
+template <int LAW, int NM, bool MIXED, int FM, bool DP>
 __device__ __forceinline__ LaneOut integrate_mp(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
     const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow, int q,
-    int gbase) {
+    int gbase, const DriveP<typename std::conditional<MIXED, float, double>::type> &dv) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
@@ -356,9 +357,40 @@ __device__ __forceinline__ LaneOut integrate_mp(
     const double lim = K.div_nm;
     double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
     int32_t st = 0;
+    R Dc = R(0);  // DP: drive term at the start of the next step
+    if constexpr (DP) Dc = dv.at(0.0);
+    // DP: the eight new drive terms of four steps (half-steps j0 .. j0 + 7), evaluated 8 / G per
+    // lane -- lane q takes j0 + q + G r -- and gathered over the group (every lane of a group
+    // holds the same parameters, so any lane's evaluation is every lane's)
+    auto drive8 = [&](double j0, R (&d)[8]) {
+        constexpr int PER = 8 / G;
+        R mine[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) mine[r] = dv.at(j0 + (double)(q + G * r));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d[k] = __shfl(mine[k / G], gbase + k % G, 64);
+    };
 
     for (int c = 0; c < nc; ++c) {
-        if (c < c_win) {
+        if (DP && c < c_win) {
+            const double jb = 2.0 * ((double)c * N);
+            int s = 0;
+            for (; s + 4 <= N; s += 4) {
+                R d[8];
+                drive8(jb + 2.0 * s + 1.0, d);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dc, d[0], d[1]);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[1], d[2], d[3]);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[3], d[4], d[5]);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[5], d[6], d[7]);
+                Dc = d[7];
+            }
+            for (; s < N; ++s) {
+                const double j = jb + 2.0 * s;
+                const R D1 = dv.at(j + 1.0), D2 = dv.at(j + 2.0);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dc, D1, D2);
+                Dc = D2;
+            }
+        } else if (c < c_win) {
             int s = 0;
             for (; s + 4 <= N; s += 4) {
                 using CR = const __attribute__((address_space(4))) R;
@@ -377,11 +409,11 @@ __device__ __forceinline__ LaneOut integrate_mp(
             const int w0 = (c - c_win) * N;
             const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
             double Un = Up ? Up[0] : 0.0;
-            for (int s = 0; s < N; ++s) {
+            // one window step: RK4, sample, lock-in and misfit sums, trace
+            auto wstep = [&](int s, R D0, R D1, R D2) {
                 const double Uc = Un;
                 if (Up) Un = Up[s + 1 < N ? s + 1 : s];
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
-                                             Dt[2 * s + 1], Dt[2 * s + 2]);
+                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, D0, D1, D2);
                 const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
                 Sc = __builtin_fma(u, Lc[s + 1], Sc);
                 Ss = __builtin_fma(u, Ls[s + 1], Ss);
@@ -392,6 +424,26 @@ __device__ __forceinline__ LaneOut integrate_mp(
                     Jd = __builtin_fma(U, U, Jd);
                 }
                 if (trow && q == 0) trow[w0 + s] = u * 1e-9;
+            };
+            if constexpr (DP) {
+                const double jb = 2.0 * ((double)c * N);
+                int s = 0;
+                for (; s + 4 <= N; s += 4) {
+                    R d[8];
+                    drive8(jb + 2.0 * s + 1.0, d);
+                    wstep(s, Dc, d[0], d[1]);
+                    wstep(s + 1, d[1], d[2], d[3]);
+                    wstep(s + 2, d[3], d[4], d[5]);
+                    wstep(s + 3, d[5], d[6], d[7]);
+                    Dc = d[7];
+                }
+                for (; s < N; ++s) {
+                    const R D1 = dv.at(jb + 2.0 * s + 1.0), D2 = dv.at(jb + 2.0 * s + 2.0);
+                    wstep(s, Dc, D1, D2);
+                    Dc = D2;
+                }
+            } else {
+                for (int s = 0; s < N; ++s) wstep(s, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
             }
         }
         // end-of-period health check, combined over the group
@@ -429,7 +481,7 @@ __device__ __forceinline__ LaneOut integrate_mp(
 
 // G lanes per trajectory; the block size is a multiple of 8, so groups never straddle a
 // workgroup and every lane of a group exits together.
-template <int LAW, int NM, bool MIXED, int FM>
+template <int LAW, int NM, bool MIXED, int FM, bool DP = false>
 __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KConst K) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
@@ -442,6 +494,8 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
     double p[kMaxParams];
     load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
     const Law<LAW, R> law(p, K);
+    DriveP<R> dv;
+    if constexpr (DP) dv = DriveP<R>(p, K, NM);
     const int64_t W = (int64_t)K.lockin * K.N;
     const double *Urow = nullptr;
     bool bad = nc < K.lockin;
@@ -460,7 +514,8 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
         if (trow && q == 0)
             for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
     } else {
-        o = integrate_mp<LAW, NM, MIXED, FM>(law, p[0] * 1e9, K, nc, Urow, trow, q, gbase);
+        o = integrate_mp<LAW, NM, MIXED, FM, DP>(law, p[0] * 1e9, K, nc, Urow, trow, q, gbase,
+                                                 dv);
     }
     if (q == 0) {
         if (A.amp) A.amp[i] = o.A;
@@ -535,17 +590,38 @@ hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStrea
     return hipGetLastError();
 }
 
+// Parameter-driven base (branch-free law form): `sh.tpl` 0 = one lane per mode, else one
+// trajectory per lane.
+template <int LAW, int NM, bool MIXED>
+hipError_t launch_dp(const FwdArgs &a, const KConst &K, FwdShape sh, hipStream_t s) {
+    if constexpr (NM > 1) {
+        if (sh.tpl == 0) {
+            constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
+            const int64_t per = sh.block / G;
+            hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree, true>),
+                               dim3((unsigned)((a.n + per - 1) / per)), dim3(sh.block), 0, s, a, K);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1, true>),
+                       dim3((unsigned)((a.n + sh.block - 1) / sh.block)), dim3(sh.block), 0, s, a,
+                       K);
+    return hipGetLastError();
+}
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
     if (K.drive_mode != AFM_DRIVE_TABLE) {
-        // parameter-driven base: one trajectory per lane with its own drive, the branch-free law
-        // form; a work-queue batch runs as a plain grid (per-group period counts are read per
-        // lane)
-        const int block = a.n < kSmallBatch ? 64 : 256;
-        hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1, true>),
-                           dim3((unsigned)((a.n + block - 1) / block)), dim3(block), 0, s, a, K);
-        return hipGetLastError();
+        // parameter-driven base: one trajectory per lane or one lane per mode, tuned like the
+        // fixed-drive shapes; a work-queue batch runs as a plain grid (per-group period counts
+        // are read per lane)
+        FwdShape sh;
+        hipError_t e = forward_shape(
+            plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM, s,
+            [&](FwdShape c) { return launch_dp<LAW, NM, MIXED>(a, K, c, s); }, &sh);
+        if (e != hipSuccess) return e;
+        return launch_dp<LAW, NM, MIXED>(a, K, sh, s);
     }
     if (a.items) {
         // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one

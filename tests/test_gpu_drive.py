@@ -124,6 +124,29 @@ def test_beam_chirp_forward(afm, orc, prec, nm, law):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("nm", [3, 8])
+def test_mode_parallel_is_bit_identical(afm, orc, prec, nm):
+    """One lane per mode and one trajectory per lane compute the same bits (ragged batch)."""
+    import torch
+
+    m = _beam_model(nm, N=500, n_cycles=3, lockin=2)
+    box = [(8, 0.0, 100e-9, 0), (9, 7500.0, 27000.0, 0), (10, 1.9e7, 2.1e7, 0)]
+    th = torch.tensor(_draw_afg(203, 30 + nm, box), device="cuda")
+    plan = afm.Plan(m, _full([0.0], 2e-9, 25.6e3, 0.0), box, precision=prec)
+    U = torch.tensor(orc.forward(m, _full([0.0], 2e-9, 25.6e3, 0.0),
+                                 want_trace=True)["trace"][None, :], device="cuda")
+    res = []
+    for tpl in (1, 0):
+        plan.set_launch_shape(64, tpl)
+        r = plan.forward_batch(th, trace=True)
+        J, st = plan.misfit(th, U)
+        res.append([r["amp"], r["phase"], r["trace"], r["status"], J, st])
+    for a, b in zip(*res):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_sinusoid_reproduces_fixed_drive(afm, orc, prec):
     """f = drive frequency, g = 0 and a = the table's base amplitude: the per-lane drive and the
     drive table describe the same motion, so the results agree to the precision's rounding."""
