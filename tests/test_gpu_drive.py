@@ -6,9 +6,10 @@ against the oracle.
   cantilevers, with and without a tip force, started at rest; mixed to the mixed-precision
   tolerances of parity.py (conditioning filter for the contact cases), FP64 to 1e-9;
 * the sinusoid at the table's own frequency and amplitude reproduces the fixed-drive path;
-* inversions of the paper's base-motion problems (App. A beam, 1000 steps of 4e-8 s from rest):
-  with the FP64 forward the swarm follows the oracle swarm step for step (1-D amplitude, 3-D
-  chirp, and per-swarm period counts); the mixed forward recovers the 2-D truth;
+* inversions of the paper's problems (App. A beam, 4e-8 s steps from rest): with the FP64
+  forward the swarm follows the oracle swarm step for step (1-D amplitude, 3-D chirp, the
+  spring sample of Sec. 4.2, and per-swarm period counts); the mixed forward recovers the 2-D
+  truth; the spring-damper sample of Sec. 4.3 forward in both precisions;
 * the adjoint of these parameters is not built: gradients and polish report unsupported."""
 import numpy as np
 import pytest
@@ -63,10 +64,12 @@ def _draw_afg(n, seed, box=_FREE_AFG):
     return np.stack([rng.uniform(lo, hi, n) for _, lo, hi, _ in box])
 
 
-def _check_forward(afm, orc, m, law_params, free, th, prec, tag):
+def _check_forward(afm, orc, m, base, free, th, prec, tag):
+    """GPU forward of the points th ([D][n] free values over the full vector `base`) against
+    the oracle."""
     import torch
 
-    P = PT.full_from_free(_full(law_params, 0.0, 0.0, 0.0), free, th)
+    P = PT.full_from_free(base, free, th)
     U = orc.forward(m, P[0], want_trace=True)["trace"] * 0.9  # a target near the first point
     plan = afm.Plan(m, P[0], free, precision=prec)
     r = plan.forward_batch(torch.tensor(th, device="cuda"), trace=True)
@@ -102,8 +105,8 @@ def _check_forward(afm, orc, m, law_params, free, th, prec, tag):
 def test_point_mass_chirp_forward(afm, orc, prec, law):
     m = _pm_model(law=law)
     th = _draw_afg(203, 1 if law == "none" else 2)  # several workgroups and a ragged tail
-    _check_forward(afm, orc, m, _DMT if law == "dmt" else [8e-9], _FREE_AFG, th, prec,
-                   f"point mass {law} {prec}")
+    _check_forward(afm, orc, m, _full(_DMT if law == "dmt" else [8e-9], 0.0, 0.0, 0.0),
+                   _FREE_AFG, th, prec, f"point mass {law} {prec}")
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
@@ -120,7 +123,8 @@ def test_beam_chirp_forward(afm, orc, prec, nm, law):
         box = _FREE_AFG
         lawp = _DMT + [10.0]
     th = _draw_afg(70, 3 + nm, box)
-    _check_forward(afm, orc, m, lawp, box, th, prec, f"{nm}-mode {law} {prec}")
+    _check_forward(afm, orc, m, _full(lawp, 0.0, 0.0, 0.0), box, th, prec,
+                   f"{nm}-mode {law} {prec}")
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
@@ -199,6 +203,25 @@ def test_invert_chirp_fp64_matches_oracle(afm, orc):
     [0, 100] nm x [7.5, 12.5] kHz x [1.9e7, 2.1e7] Hz/s."""
     c = W.base_motion("3d_chirp")
     _invert_vs_oracle(afm, orc, c["model"], c["params"], c["free"], c["params"], 24, 4, 5, 1e-3)
+
+
+def test_invert_spring_fp64_matches_oracle(afm, orc):
+    """The paper's elastic problem (Sec. 4.2): App. A drive known, Hooke sample (h, k) unknown,
+    10000 steps from rest; a short swarm follows the oracle's step for step."""
+    c = W.paper_inversion("spring")
+    _invert_vs_oracle(afm, orc, c["model"], c["params"], c["free"], c["params"], 16, 3, 9,
+                      c["cutoff"])
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_spring_damper_forward(afm, orc, prec):
+    """The paper's viscoelastic problem (Sec. 4.3): spring-damper sample in contact over the
+    later periods, points drawn from its (k, zeta_s) box."""
+    c = W.paper_inversion("spring_damper")
+    m = dict(c["model"], n_cycles=4, lockin_cycles=2)
+    rng = np.random.default_rng(17)
+    th = np.stack([rng.uniform(lo, hi, 48) for _, lo, hi, _ in c["free"]])
+    _check_forward(afm, orc, m, c["params"], c["free"], th, prec, f"sd {prec}")
 
 
 def test_invert_uneven_cycles_fp64_matches_oracle(afm, orc):

@@ -15,7 +15,7 @@ the paper lists as its extension (adhesion / van der Waals, Sec. 5):
 * ``c4`` LJ-type law, 4 parameters, 2048 points for the adjoint gradient, 1000 x 256 steps.
 * ``c5`` 3-mode beam, Kelvin-Voigt contact + vdW, 5 parameters, 16384 x 300, 2000 x 512 steps.
 
-``base_motion`` describes the paper's base-motion inversions (Sec. 4.1) on its 8-mode beam.
+``paper_inversion`` describes the paper's own inversions (Sec. 4) on its 8-mode beam.
 
 Separations z_c are *not* computed here: they follow from the set-point by the method's own
 amplitude feedback and are stored in ``tests/golden/setpoint_zc.json`` by a script that calls
@@ -89,43 +89,75 @@ CONFIGS = {
 }
 
 
-# The paper's base-motion inversions (Sec. 4.1): the App. A cantilever -- 8 Euler-Bernoulli
-# modes, first at 25468.9 Hz, L = 525 um, E = 1.76e11 Pa, section 35 x 5 um, so
-# k = 3 E I / L^3 with I = w h^3 / 12 -- started at rest with no tip force (a free tip, z_c = 0),
-# n_t = 1000 RK4 steps of 4e-8 s (one period of a 25 kHz time unit), misfit over all of them.
-# The base motion y_b = a sin(2 pi (f + g t) t) (Eq. 9 with g = 0, Eq. 10) is the unknown.  The
-# paper gives no damping for this beam; Q = 400 per mode (one period from rest barely feels it).
-# The paper states 512 particles for the 1-D runs; the others use the same.
+# The paper's own inversions (Sec. 4) on its App. A cantilever -- 8 Euler-Bernoulli modes,
+# first at 25468.9 Hz, L = 525 um, E = 1.76e11 Pa, section 35 x 5 um, so k = 3 E I / L^3 with
+# I = w h^3 / 12 -- started at rest, RK4 steps of 4e-8 s (1000 per period of a 25 kHz time unit),
+# misfit over the whole trajectory.  The paper gives no damping for this beam: Q = 400 per mode.
+# It states 512 particles for the 1-D runs; every case uses the same.
+#
+# Base motion (Sec. 4.1): y_b = a sin(2 pi (f + g t) t) (Eq. 9 with g = 0, Eq. 10) is the
+# unknown; a free tip (no force law, z_c = 0), n_t = 1000 steps.
+#
+# Sample (Sec. 4.2, 4.3): the base motion is known -- App. A's drive, 5 nm at 25.5 kHz -- and the
+# tip meets a Hooke spring (Eq. 11) or spring-damper (Eq. 12) sample h = 50 nm away
+# (z_c = h; the gap closes when the tip deflects 50 nm towards the sample); n_t = 10000 steps
+# (the top of the range Sec. 4.1 tried), so that the tip, ringing up from rest, presses into the
+# sample over the later periods.  The printed spring-damper truth zeta_s = 0.1 N s/m (box
+# [0, 2]) puts zeta_s dt / m_1 near 77 for this beam, far outside explicit RK4's stability
+# interval: every trajectory in contact diverges, the truth included.  zeta_s and its box are
+# scaled by 1e-4 (truth 1e-5 N s/m, box [0, 2e-4]), the largest power of ten that keeps the box
+# stable.
 _EB_I = 35e-6 * 5e-6**3 / 12.0
 _BEAM = dict(n_modes=8, law="none", k=3.0 * 1.76e11 * _EB_I / 525e-6**3, f0=25468.9,
              drive_freq=25e3, q=[400.0] * 8, free_amplitude=20 * NM, ic="rest", div_limit=1e4,
              steps_per_cycle=1000, n_cycles=1, lockin_cycles=1, drive="params")
+_APP_A_DRIVE = (5 * NM, 25500.0, 0.0)
 
-BASE_MOTION = {
-    "1d": dict(truth=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)], cutoff=1e-2,
+PAPER_INVERSIONS = {
+    "1d": dict(base=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)], cutoff=1e-2,
                paper=dict(generations=3.0, ms=48.0, note="mean, 512 particles, cut-off 0.01")),
-    "1d_tight": dict(truth=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)],
+    "1d_tight": dict(base=(2 * NM, 25600.0, 0.0), free=[(8, 0.0, 100 * NM, False)],
                      cutoff=1e-3, paper=dict(generations=7.99, ms=128.0, note="cut-off 0.001")),
-    "2d": dict(truth=(2 * NM, 25600.0, 0.0),
+    "2d": dict(base=(2 * NM, 25600.0, 0.0),
                free=[(8, 0.0, 100 * NM, False), (9, 25100.0, 26100.0, False)], cutoff=1e-2,
                paper=dict(generations=19.0458, ms=320.0, note="a and f, a 1000 Hz box")),
-    "3d_chirp": dict(truth=(2 * NM, 10e3, 2e7),
+    "3d_chirp": dict(base=(2 * NM, 10e3, 2e7),
                      free=[(8, 0.0, 100 * NM, False), (9, 7500.0, 12500.0, False),
                            (10, 1.9e7, 2.1e7, False)], cutoff=1e-2,
                      paper=dict(generations=14.9, ms=240.0, note="a, f, g (chirp)")),
+    "spring": dict(law="hooke", law_params=(50 * NM, 4.0), base=_APP_A_DRIVE, n_cycles=10,
+                   free=[(0, 0.0, 100 * NM, False), (1, 0.0, 25.0, False)], cutoff=5e-4,
+                   paper=dict(generations=18.0, ms=288.0,
+                              note="h and k unknown, cut-off J_L2 = 0.0005; box not printed")),
+    "spring_damper": dict(law="sd", law_params=(50 * NM, 4.0, 1e-5), base=_APP_A_DRIVE,
+                          n_cycles=10, free=[(1, 0.0, 25.0, False), (2, 0.0, 2e-4, False)],
+                          cutoff=5e-4,
+                          paper=dict(generations=16.0, ms=256.0,
+                                     note="k and zeta_s unknown, h known; zeta_s scaled 1e-4")),
 }
+BASE_MOTION = ("1d", "1d_tight", "2d", "3d_chirp")
+
+
+def paper_inversion(case: str) -> dict:
+    """One of the paper's inversions: model, full 12-entry parameter vector at the truth (the
+    law's first, z_c at 0; a, f, g at 8, 9, 10), free-parameter spec, cut-off on sqrt(J)."""
+    c = PAPER_INVERSIONS[case]
+    eb = beam_modes(8)
+    nc = int(c.get("n_cycles", 1))
+    model = dict(_BEAM, law=c.get("law", "none"), ratio=list(eb["ratio"]), gain=list(eb["gain"]),
+                 n_cycles=nc, lockin_cycles=nc)
+    p = np.zeros(12)
+    lp = c.get("law_params", (0.0,))
+    p[: len(lp)] = lp
+    p[8], p[9], p[10] = c["base"]
+    return dict(model=model, params=p, free=[tuple(f) for f in c["free"]], cutoff=c["cutoff"],
+                paper=dict(c["paper"]))
 
 
 def base_motion(case: str) -> dict:
-    """One of the paper's base-motion problems: model, full 12-entry parameter vector at the
-    truth (law slot 0 = z_c = 0; a, f, g at 8, 9, 10), free-parameter spec, cut-off."""
-    c = BASE_MOTION[case]
-    eb = beam_modes(8)
-    model = dict(_BEAM, ratio=list(eb["ratio"]), gain=list(eb["gain"]))
-    p = np.zeros(12)
-    p[8], p[9], p[10] = c["truth"]
-    return dict(model=model, params=p, free=[tuple(f) for f in c["free"]], cutoff=c["cutoff"],
-                paper=dict(c["paper"]))
+    """One of the paper's base-motion problems (Sec. 4.1); see paper_inversion."""
+    assert case in BASE_MOTION
+    return paper_inversion(case)
 
 
 def stored_setpoints() -> dict:
