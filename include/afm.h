@@ -261,6 +261,20 @@ afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
                       double cutoff, int32_t lbfgs_steps, int32_t lbfgs_topk, double *best_theta,
                       double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream);
 
+/* Modes of a uniform clamped-free Euler-Bernoulli cantilever (Sec. 3.2, Eq. 6-7; App. B), for
+ * building afm_problem's ratio and gain: beta_i L from cos(beta L) cosh(beta L) + 1 = 0 (Newton),
+ * mode shapes Phi_i in the overflow-free exponential form of Eq. 6 with Eq. 7's G -- its
+ * denominator read as 2 e^{-beta L} cos(beta L) + e^{-2 beta L} + 1, since the printed minus on
+ * e^{-2 beta L} violates the free-end conditions -- normalised at the tip (phi_i = Phi_i /
+ * Phi_i(L)), integrals by Simpson's rule on n_points points (odd, >= 3; the paper uses 501).
+ * Outputs (host arrays of n_modes, 1 <= n_modes <= 8): ratio[i] = w_i / w_1 = (beta_i / beta_1)^2;
+ * gain[i] = gamma_i = int phi_i dx / int phi_i^2 dx (the base-drive participation of mode i in
+ * Eq. 2).  f1 (optional): the first natural frequency beta_1^2 sqrt(E I / (mu L^4)) / (2 pi) in
+ * Hz from the modulus E (Pa), section moment I (m^4), mass per length mu (kg/m) and length L
+ * (m); NaN unless all four are positive.  Host computation only (no device, no stream). */
+afm_status afm_beam_modes(int32_t n_modes, int32_t n_points, double E, double I, double mu,
+                          double L, double *ratio, double *gain, double *f1);
+
 /* Text of the calling thread's last error ("" if none). */
 const char *afm_last_error(void);
 

@@ -42,7 +42,7 @@ ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
            "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-           "afm_last_error", "afm_version")
+           "afm_beam_modes", "afm_last_error", "afm_version")
 
 
 class AfmError(RuntimeError):
@@ -96,10 +96,12 @@ def lib() -> C.CDLL:
     L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
     L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.afm_invert.argtypes = [vp, i32, vp, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
+    L.afm_beam_modes.argtypes = [i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
-              "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert"):
+              "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
+              "afm_beam_modes"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -109,6 +111,15 @@ def _check(code: int, what: str):
     if code != 0:
         msg = lib().afm_last_error().decode()
         raise AfmError(f"{what} failed (status {code}): {msg}")
+
+
+def beam_modes(n_modes: int, n_points: int = 501, E=0.0, I=0.0, mu=0.0, L=0.0) -> dict:
+    """Clamped-free Euler-Bernoulli modes (afm_beam_modes, host only): frequency ratios, base-drive
+    gains of the tip-normalised modes and, from the beam's properties, the first frequency."""
+    ratio, gain, f1 = (C.c_double * n_modes)(), (C.c_double * n_modes)(), C.c_double()
+    _check(lib().afm_beam_modes(int(n_modes), int(n_points), float(E), float(I), float(mu),
+                                float(L), ratio, gain, C.byref(f1)), "afm_beam_modes")
+    return {"ratio": list(ratio), "gain": list(gain), "f1": f1.value}
 
 
 def make_problem(model: dict, params, free=(), pso=None, polish="plan") -> _Problem:

@@ -1,0 +1,106 @@
+"""The library's modal set-up (afm_beam_modes, host code: no GPU needed) against the paper and
+the oracle.
+
+* App. A: the first natural frequency from the printed length, modulus, section and mass per
+  length is the printed 25468.9 Hz;
+* eigenvalues: the classical clamped-free roots beta_i L = 1.875104, 4.694091, 7.854757,
+  10.995541, 14.137168, 17.278760, 20.420352, 23.561945 (printed to 7 digits in every
+  vibrations text) give the ratios to 1e-6;
+* gains against a 40-digit reference (mpmath): the textbook hyperbolic mode shape
+  cosh - cos - sigma (sinh - sin) -- not Eq. 6's exponential form -- with roots from mpmath's
+  findroot, integrated by the same 501-point Simpson rule (1e-12: only the library's rounding
+  is left) and exactly by quadrature (the Simpson error at 501 points, below 1e-7);
+* ratios and gains equal the oracle's independent set-up for 1 .. 3 modes to 1e-12 (for higher
+  modes the oracle forms Eq. 6's (G - 1) e^{beta x} by cancellation, good to about
+  1e-16 e^{beta L} relative, which the library's form avoids);
+* invalid arguments are rejected."""
+import ctypes as C
+import json
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def afm():
+    import paper_1109_0334_amd as afm
+
+    try:
+        afm.lib()
+    except Exception as e:  # the library is built by __graft_entry__.build()
+        pytest.skip(f"libafm.so not built: {e}")
+    return afm
+
+
+def test_first_frequency_appendix_a(afm):
+    g = json.load(open(os.path.join(HERE, "golden", "appendix_a_cantilever.json")))
+    I = g["width_m"] * g["height_m"] ** 3 / 12.0
+    r = afm.beam_modes(1, 501, g["youngs_modulus_Pa"], I, g["mass_per_length_kg_per_m"],
+                       g["length_m"])
+    assert abs(r["f1"] - g["first_natural_frequency_Hz"]) < 0.05
+
+
+def test_ratios_from_classical_roots(afm):
+    bl = np.array([1.875104, 4.694091, 7.854757, 10.995541, 14.137168, 17.278760, 20.420352,
+                   23.561945])
+    r = afm.beam_modes(8)
+    np.testing.assert_allclose(r["ratio"], (bl / bl[0]) ** 2, rtol=1e-6)
+    assert np.isnan(r["f1"])  # no beam properties given
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_matches_oracle_setup(afm, orc, n):
+    r = afm.beam_modes(n, 501)
+    o = orc.eb_modes(n, 501)
+    np.testing.assert_allclose(r["ratio"], o["ratio"], rtol=1e-12)
+    np.testing.assert_allclose(r["gain"], o["gain"], rtol=1e-12)
+
+
+def _mp_reference(n, npts):
+    """40-digit gains of tip-normalised clamped-free modes: Simpson on npts points and exact."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    simpson, exact = [], []
+    for i in range(1, n + 1):
+        b = mp.findroot(lambda z: mp.cos(z) * mp.cosh(z) + 1, (2 * i - 1) * mp.pi / 2
+                        if i > 1 else mp.mpf("1.875"))
+        sig = (mp.cosh(b) + mp.cos(b)) / (mp.sinh(b) + mp.sin(b))
+
+        def phi(s, b=b, sig=sig):
+            return mp.cosh(b * s) - mp.cos(b * s) - sig * (mp.sinh(b * s) - mp.sin(b * s))
+
+        tip = phi(mp.mpf(1))
+        ds = mp.mpf(1) / (npts - 1)
+        s1 = s2 = mp.mpf(0)
+        for k in range(npts):
+            w = 1 if k in (0, npts - 1) else (4 if k % 2 else 2)
+            v = phi(k * ds) / tip
+            s1 += w * v
+            s2 += w * v * v
+        simpson.append(float(s1 / s2))
+        exact.append(float(mp.quad(lambda s: phi(s) / tip, [0, 1]) /
+                           mp.quad(lambda s: (phi(s) / tip) ** 2, [0, 1])))
+    return np.array(simpson), np.array(exact)
+
+
+def test_gains_against_high_precision_reference(afm):
+    simpson, exact = _mp_reference(8, 501)
+    a = np.array(afm.beam_modes(8, 501)["gain"])
+    np.testing.assert_allclose(a, simpson, rtol=1e-12)
+    assert np.max(np.abs(a / exact - 1)) < 1e-7  # Simpson's error at the paper's 501 points
+    b = np.array(afm.beam_modes(8, 4001)["gain"])
+    np.testing.assert_allclose(b, exact, rtol=1e-11)
+    # the first three gains quoted for tip-normalised modes (int phi / int phi^2 with
+    # int phi^2 = L / 4): 4 x 0.391496, -4 x 0.216968, 4 x 0.127213
+    np.testing.assert_allclose(a[:3], [1.565984, -0.867872, 0.508851], atol=2e-6)
+
+
+@pytest.mark.parametrize("n,npts", [(0, 501), (9, 501), (3, 500), (3, 1)])
+def test_invalid_arguments(afm, n, npts):
+    r = (C.c_double * 9)()
+    g = (C.c_double * 9)()
+    assert afm.lib().afm_beam_modes(n, npts, 0.0, 0.0, 0.0, 0.0, r, g, None) == 1
+    assert afm.lib().afm_last_error().decode()
