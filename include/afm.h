@@ -105,7 +105,7 @@ enum { AFM_ST_NONFINITE = 1, AFM_ST_DIVERGED = 2, AFM_ST_BAD_INPUT = 4 };
 
 /* Problem description, copied by value into a plan (FP: Sec. 2.2; IP search box: Sec. 3.4). */
 typedef struct afm_problem {
-    int32_t n_modes;         /* 1 (point mass) .. 4, or 8 (the paper's beam), tip-normalised  */
+    int32_t n_modes;         /* 1 (point mass) .. 8 (the paper's beam), tip-normalised modes  */
     int32_t law;             /* AFM_LAW_*                                                     */
     int32_t steps_per_cycle; /* N, RK4 steps per drive period, 4 .. 4096                      */
     int32_t n_cycles;        /* drive periods integrated (default per trajectory)             */
@@ -166,7 +166,7 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * with a new combination runs the launch once per candidate -- workgroups of 64, 128 or 256
  * lanes, times one trajectory per lane, two trajectories per lane (point-mass problems with the
  * fixed drive and without per-trajectory period counts) or one lane per mode (problems with
- * several modes: 2 lanes per trajectory for 2 modes, 4 for 3 or 4, 8 for 8; the paper's mapping
+ * several modes: 2 lanes per trajectory for 2 modes, 4 for 3 or 4, 8 for 5 to 8; the paper's mapping
  * of modes to threads, Sec. 3.2) --
  * times each with events and keeps the default shape unless another is at least 2 % faster;
  * that call synchronises the stream.  Under stream

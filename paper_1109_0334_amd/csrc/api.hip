@@ -45,8 +45,6 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     if (precision != AFM_PREC_MIXED && precision != AFM_PREC_FP64)
         return fail(AFM_ERR_INVALID, "precision must be AFM_PREC_MIXED or AFM_PREC_FP64");
     if (pr.n_modes < 1 || pr.n_modes > kMaxModes) return fail(AFM_ERR_INVALID, "n_modes out of range");
-    if (pr.n_modes > 4 && pr.n_modes < 8)
-        return fail(AFM_ERR_UNSUPPORTED, "5 to 7 modes are not built (1 to 4, or 8)");
     if (pr.law < 0 || pr.law > AFM_LAW_NONE) return fail(AFM_ERR_INVALID, "unknown law");
     if (pr.steps_per_cycle < 4 || pr.steps_per_cycle > kMaxSteps)
         return fail(AFM_ERR_INVALID, "steps_per_cycle must be in [4, 4096]");

@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
 }
 
 // Mode-parallel forward: G lanes per trajectory (G = 2 for two modes, 4 for three or four, 8 for
-// eight),
+// five to eight),
 // lane q integrating mode q with the shared force (rk4_step_mp).  Same operations in the same
 // order as the one-lane kernel, so the same bits; the time loops, health checks and window
 // sums are group-uniform (every lane of a group sees the same gap, deflection and flags).  DP:
@@ -648,6 +648,9 @@ hipError_t launch_modes(const afm_plan *plan, const FwdArgs &a, const KConst &K,
     case 2: return launch_t<LAW, 2, MIXED>(plan, a, K, s);
     case 3: return launch_t<LAW, 3, MIXED>(plan, a, K, s);
     case 4: return launch_t<LAW, 4, MIXED>(plan, a, K, s);
+    case 5: return launch_t<LAW, 5, MIXED>(plan, a, K, s);
+    case 6: return launch_t<LAW, 6, MIXED>(plan, a, K, s);
+    case 7: return launch_t<LAW, 7, MIXED>(plan, a, K, s);
     case 8: return launch_t<LAW, 8, MIXED>(plan, a, K, s);
     }
     return hipErrorInvalidValue;

@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
 
 // ------------------------------------------------------------------------------------------
 // Mode-parallel adjoint: G lanes per trajectory (G = 2 for two modes, 4 for three or four, 8 for
-// eight),
+// five to eight),
 // lane q owning mode q in the forward pass, the checkpoints, the segment buffer and the reverse
 // sweep (the transposed stage Jacobians are per mode apart from the force terms, whose sums over
 // modes are butterfly sums over the group).  The same operations in the same order as k_grad,
@@ -635,6 +635,9 @@ hipError_t launch_modes(const GradArgs &a, const KConst &K, hipStream_t s) {
     case 2: return launch_t<LAW, 2, MIXED>(a, K, s);
     case 3: return launch_t<LAW, 3, MIXED>(a, K, s);
     case 4: return launch_t<LAW, 4, MIXED>(a, K, s);
+    case 5: return launch_t<LAW, 5, MIXED>(a, K, s);
+    case 6: return launch_t<LAW, 6, MIXED>(a, K, s);
+    case 7: return launch_t<LAW, 7, MIXED>(a, K, s);
     case 8: return launch_t<LAW, 8, MIXED>(a, K, s);
     }
     return hipErrorInvalidValue;

@@ -14,12 +14,17 @@ namespace afm {
 //
 // Sum over modes in the order a butterfly over the lanes of a mode-parallel group produces:
 // sequential up to three modes ((x0 + x1) + x2, the missing fourth lane adding an exact zero),
-// pairwise for four and eight.  The one-lane and the mode-parallel kernels use this same order, so they
-// compute identical bits.
+// pairwise for four to eight (lanes without a mode add exact zeros: five modes give
+// ((x0 + x1) + (x2 + x3)) + x4).  The one-lane and the mode-parallel kernels use this same
+// order, so they compute identical bits.
 template <int NM, typename R>
 __device__ __forceinline__ R mode_sum(const R (&x)[NM]) {
-    if constexpr (NM == 8) {
-        return ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+    if constexpr (NM > 4) {
+        const R lo = (x[0] + x[1]) + (x[2] + x[3]);
+        if constexpr (NM == 5) return lo + x[4];
+        else if constexpr (NM == 6) return lo + (x[4] + x[5]);
+        else if constexpr (NM == 7) return lo + ((x[4] + x[5]) + x[6]);
+        else return lo + ((x[4] + x[5]) + (x[6] + x[7]));
     } else if constexpr (NM == 4) {
         return (x[0] + x[1]) + (x[2] + x[3]);
     } else {
@@ -123,7 +128,7 @@ __device__ __forceinline__ double sample(const R (&x)[NM], const R (&cx)[NM], do
 
 // ------------------------------------------------------------------------------------------
 // Mode-parallel form (the paper's own mapping of modes to threads, Sec. 3.2): the G lanes of a
-// group (G = 2 for two modes, 4 for three or four, 8 for eight) hold one trajectory, lane q its mode q (a
+// group (G = 2 for two modes, 4 for three or four, 8 for five to eight) hold one trajectory, lane q its mode q (a
 // lane without a mode carries an exact zero).  The gap and gap rate are butterfly sums over the
 // group (DPP lane swaps, so the sum costs one add per butterfly level); every lane evaluates the
 // force law on the same sums and advances only its own mode.

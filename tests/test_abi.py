@@ -128,13 +128,3 @@ def test_launch_shape_arguments_checked(afm):
     L = afm.lib()
     assert L.afm_set_launch_shape(None, 64, 1) == 1
     assert afm.lib().afm_last_error().decode()
-
-
-@pytest.mark.parametrize("nm", [5, 6, 7])
-def test_unbuilt_mode_counts_reported(afm, nm):
-    """1-4 and 8 modes are built; 5-7 are refused as unsupported (not as invalid)."""
-    m = dict(_base_model(), n_modes=nm, q=[400.0] * nm, ratio=list(range(1, nm + 1)),
-             gain=[1.0] * nm)
-    prob = afm.make_problem(m, [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9])
-    h = C.c_void_p()
-    assert afm.lib().afm_plan_create(C.byref(prob), 0, C.byref(h)) == 4 and not h.value
