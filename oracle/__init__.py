@@ -76,6 +76,8 @@ def lib() -> C.CDLL:
         L.orc_trajectory.restype = C.c_int
         L.orc_forward.argtypes = [mp, dp, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_forward.restype = C.c_int
+        L.orc_forward_points.argtypes = [mp, dp, C.c_int32, C.c_int32, dp, dp, dp, dp]
+        L.orc_forward_points.restype = C.c_int
         L.orc_lockin.argtypes = [dp, C.c_int64, C.c_int32, C.c_int64, dp, dp]
         L.orc_misfit.argtypes = [dp, dp, C.c_int64]
         L.orc_misfit.restype = C.c_double
@@ -208,6 +210,20 @@ def forward(m: dict, p, target=None, n_cycles=None, want_trace=False):
     st = L.orc_forward(C.byref(mo), _dp(p), nc, _dp(U), C.byref(A), C.byref(phi), C.byref(J),
                        _dp(tr))
     return {"status": st, "A": A.value, "phi": phi.value, "J": J.value, "trace": tr}
+
+
+def forward_points(m: dict, p, weights, n_cycles=None, want_trace=False):
+    """Deflection at points along the beam: weights [n_pts][n_modes] (Phi_i(x_k) / Phi_i(L));
+    returns dict(status, A [n_pts], phi [n_pts], trace [n_pts][W] or None)."""
+    L, mo = lib(), make_model(m)
+    nc = int(m["n_cycles"] if n_cycles is None else n_cycles)
+    w = np.ascontiguousarray(np.atleast_2d(np.asarray(weights, dtype=np.float64)))
+    assert w.shape[1] == mo.n_modes
+    k = w.shape[0]
+    A, phi = np.empty(k), np.empty(k)
+    tr = np.empty((k, window_len(m))) if want_trace else None
+    st = L.orc_forward_points(C.byref(mo), _dp(_pv(p)), nc, k, _dp(w), _dp(A), _dp(phi), _dp(tr))
+    return {"status": st, "A": A, "phi": phi, "trace": tr}
 
 
 def forward_batch(m: dict, P, targets=None, target_id=None, n_cycles=None):

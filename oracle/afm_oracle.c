@@ -306,13 +306,24 @@ static double tip(const orc_derived *dv, const double *y) {
 /* Trajectory                                                                                 */
 /* ------------------------------------------------------------------------------------------ */
 
+/* Deflection at n_pts points along the beam from the tip-normalised modal coordinates (App. B,
+ * Eq. 13): u(x_k) = sum_i w[k][i] y_i with w[k][i] = Phi_i(x_k) / Phi_i(L). */
+static double point(const orc_derived *dv, const double *w, const double *y) {
+    double u = 0.0;
+    for (int i = 0; i < dv->m; i++) u += w[i] * y[i];
+    return u;
+}
+
 /* Integrate n_cycles drive periods (N_tot = n_cycles * N steps) from y0 (NULL: the model's
  * initial condition).  States are y_n, n = 0..N_tot, y_n at t_n = n h.  Writes the tip deflection
- * u_n (and its rate into ud_out if non-NULL) for n = N_tot - n_out + 1 .. N_tot.  At the end of
- * every period the state is checked: non-finite => NONFINITE, |u| > div_limit * A0 => DIVERGED;
- * integration stops there and every output sample is NaN.  Returns the status bits. */
-int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const double *y0,
-                   int64_t n_out, double *u_out, double *ud_out, double *y_end) {
+ * u_n (and its rate into ud_out if non-NULL) for n = N_tot - n_out + 1 .. N_tot, and, for each of
+ * n_pts points with weights w ([n_pts][m]), the deflection there into pts_out ([n_pts][n_out]).
+ * At the end of every period the state is checked: non-finite => NONFINITE,
+ * |u| > div_limit * A0 => DIVERGED; integration stops there and every output sample is NaN.
+ * Returns the status bits. */
+static int trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const double *y0,
+                      int64_t n_out, double *u_out, double *ud_out, double *y_end, int n_pts,
+                      const double *w, double *pts_out) {
     orc_derived dv;
     derive(mo, &dv);
     int m = dv.m, N = mo->steps_per_cycle;
@@ -325,15 +336,17 @@ int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const
     for (int64_t k = 0; k < n_out; k++) {
         if (u_out) u_out[k] = NAN;
         if (ud_out) ud_out[k] = NAN;
+        for (int q = 0; q < n_pts; q++) pts_out[q * n_out + k] = NAN;
     }
-    if (first <= 0 && u_out) { /* the initial state is inside the output range */
+    if (first <= 0) { /* the initial state is inside the output range */
         int64_t k = 0 - first;
-        u_out[k] = tip(&dv, y);
+        if (u_out) u_out[k] = tip(&dv, y);
         if (ud_out) {
             double v = 0.0;
             for (int i = 0; i < m; i++) v += y[m + i];
             ud_out[k] = v;
         }
+        for (int q = 0; q < n_pts; q++) pts_out[q * n_out + k] = point(&dv, w + q * m, y);
     }
     int status = 0;
     for (int64_t n = 0; n < Ntot; n++) {
@@ -346,6 +359,7 @@ int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const
                 for (int i = 0; i < m; i++) v += y[m + i];
                 ud_out[idx] = v;
             }
+            for (int q = 0; q < n_pts; q++) pts_out[q * n_out + idx] = point(&dv, w + q * m, y);
         }
         if ((n + 1) % N == 0) {
             double u = tip(&dv, y);
@@ -358,6 +372,7 @@ int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const
                 for (int64_t k = 0; k < n_out; k++) {
                     if (u_out) u_out[k] = NAN;
                     if (ud_out) ud_out[k] = NAN;
+                    for (int q = 0; q < n_pts; q++) pts_out[q * n_out + k] = NAN;
                 }
                 break;
             }
@@ -365,6 +380,11 @@ int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const
     }
     if (y_end) memcpy(y_end, y, sizeof(double) * 2 * m);
     return status;
+}
+
+int orc_trajectory(const orc_model *mo, const double *p, int32_t n_cycles, const double *y0,
+                   int64_t n_out, double *u_out, double *ud_out, double *y_end) {
+    return trajectory(mo, p, n_cycles, y0, n_out, u_out, ud_out, y_end, 0, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -421,6 +441,24 @@ int orc_forward(const orc_model *mo, const double *p, int32_t n_cycles, const do
         *J = INFINITY;
     }
     if (trace) memcpy(trace, u, sizeof(double) * W);
+    free(u);
+    return st;
+}
+
+/* Deflection at n_pts points along the beam (the paper's deflection points, n_dp, Sec. 3.2):
+ * weights w [n_pts][m] with w[k][i] = Phi_i(x_k) / Phi_i(L); per point the lock-in amplitude A
+ * and phase phi over the window and, if trace is non-NULL, the window deflection
+ * ([n_pts][W], m).  Failed trajectories give NaN.  Returns the status bits. */
+int orc_forward_points(const orc_model *mo, const double *p, int32_t n_cycles, int32_t n_pts,
+                       const double *w, double *A, double *phi, double *trace) {
+    int64_t N = mo->steps_per_cycle, W = (int64_t)mo->lockin_cycles * N;
+    double *u = (double *)malloc(sizeof(double) * W * (n_pts > 0 ? n_pts : 1));
+    int st = trajectory(mo, p, n_cycles, NULL, W, NULL, NULL, NULL, n_pts, w, u);
+    for (int q = 0; q < n_pts; q++) {
+        if (st == 0) orc_lockin(u + q * W, W, (int32_t)N, 1, A + q, phi + q);
+        else A[q] = phi[q] = NAN;
+    }
+    if (trace) memcpy(trace, u, sizeof(double) * W * n_pts);
     free(u);
     return st;
 }
