@@ -187,6 +187,21 @@ afm_status afm_forward_batch(afm_plan *plan, int64_t n, const double *theta,
                              const int32_t *n_cycles, double *amp, double *phase, double *trace,
                              int32_t *status, afm_stream_t stream);
 
+/* Deflection at points along the beam for n parameter points (the paper's deflection points,
+ * n_dp, Sec. 3.2): u(x_k, t) = sum_i w[k][i] q_i(t) over the tip-normalised modal coordinates
+ * q_i (App. B, Eq. 13), with weights (host, [n_points][n_modes]) w[k][i] = Phi_i(x_k) / Phi_i(L)
+ * (afm_beam_shapes gives them for a uniform cantilever; all ones is the tip).  1 <= n_points
+ * <= 16.  theta, n_cycles as in afm_forward_batch.  Outputs (device): amp, phase [n_points][n]
+ * -- each point's lock-in amplitude (m) and phase over the window --, trace [n_points][n][W]
+ * (m) or NULL, status [n]; failed trajectories give NaN.  The forward solve is afm_forward_batch's
+ * (same launch shapes and bits); the window's modal coordinates go through a plan-owned
+ * workspace of n_modes x W x 8 bytes per trajectory, at most 1 GiB (larger batches run in
+ * chunks), grown on demand. */
+afm_status afm_forward_points(afm_plan *plan, int64_t n, const double *theta,
+                              const int32_t *n_cycles, int32_t n_points, const double *weights,
+                              double *amp, double *phase, double *trace, int32_t *status,
+                              afm_stream_t stream);
+
 /* Misfit J (Eq. 5 on the lock-in window, normalised) of n parameter points against measured
  * traces.  targets: [n_targets][W] FP64 deflections in m on the window samples (the states after
  * steps N_tot - W + 1 .. N_tot); target_id: [n] row of targets per point, or NULL for row 0
@@ -274,6 +289,12 @@ afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
  * (m); NaN unless all four are positive.  Host computation only (no device, no stream). */
 afm_status afm_beam_modes(int32_t n_modes, int32_t n_points, double E, double I, double mu,
                           double L, double *ratio, double *gain, double *f1);
+
+/* Tip-normalised mode shapes of a uniform clamped-free cantilever (the shapes of
+ * afm_beam_modes) at n_x points x[k] in units of L (0 = clamped base, 1 = tip):
+ * w[k * n_modes + i] = Phi_i(x_k L) / Phi_i(L), the weights afm_forward_points takes.  1 <=
+ * n_modes <= 8, 0 <= x[k] <= 1.  Host computation only. */
+afm_status afm_beam_shapes(int32_t n_modes, int32_t n_x, const double *x, double *w);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *afm_last_error(void);

@@ -42,7 +42,8 @@ ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
            "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-           "afm_beam_modes", "afm_last_error", "afm_version")
+           "afm_forward_points", "afm_beam_modes", "afm_beam_shapes", "afm_last_error",
+           "afm_version")
 
 
 class AfmError(RuntimeError):
@@ -97,11 +98,13 @@ def lib() -> C.CDLL:
     L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.afm_invert.argtypes = [vp, i32, vp, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
     L.afm_beam_modes.argtypes = [i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp]
+    L.afm_beam_shapes.argtypes = [i32, i32, vp, vp]
+    L.afm_forward_points.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
               "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-              "afm_beam_modes"):
+              "afm_beam_modes", "afm_beam_shapes", "afm_forward_points"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -120,6 +123,16 @@ def beam_modes(n_modes: int, n_points: int = 501, E=0.0, I=0.0, mu=0.0, L=0.0) -
     _check(lib().afm_beam_modes(int(n_modes), int(n_points), float(E), float(I), float(mu),
                                 float(L), ratio, gain, C.byref(f1)), "afm_beam_modes")
     return {"ratio": list(ratio), "gain": list(gain), "f1": f1.value}
+
+
+def beam_shapes(n_modes: int, x) -> np.ndarray:
+    """Tip-normalised clamped-free mode shapes at x (units of L): [len(x)][n_modes] weights for
+    Plan.forward_points (afm_beam_shapes, host only)."""
+    x = np.ascontiguousarray(np.atleast_1d(np.asarray(x, dtype=np.float64)))
+    w = np.empty((x.size, int(n_modes)))
+    _check(lib().afm_beam_shapes(int(n_modes), x.size, x.ctypes.data, w.ctypes.data),
+           "afm_beam_shapes")
+    return w
 
 
 def make_problem(model: dict, params, free=(), pso=None, polish="plan") -> _Problem:
@@ -257,6 +270,26 @@ class Plan:
         nc = _dev_i32(n_cycles, self.device)
         _check(lib().afm_forward_batch(self._h, n, _ptr(theta), _ptr(nc), _ptr(amp), _ptr(phase),
                                        _ptr(tr), _ptr(status), _stream()), "afm_forward_batch")
+        return {"amp": amp, "phase": phase, "status": status, "trace": tr}
+
+    def forward_points(self, theta, weights, n_cycles=None, trace=False):
+        """Deflection at points along the beam: weights [n_points][n_modes] (host) ->
+        dict(amp, phase [n_points][n], status [n], trace [n_points][n][W])."""
+        import torch
+
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, -1) if self.n_free else \
+            torch.empty(0, 1, dtype=torch.float64, device=self.device)
+        n = theta.shape[1]
+        w = np.ascontiguousarray(np.atleast_2d(np.asarray(weights, dtype=np.float64)))
+        k = w.shape[0]
+        amp = torch.empty(k, n, dtype=torch.float64, device=self.device)
+        phase = torch.empty_like(amp)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        tr = torch.empty(k, n, self.W, dtype=torch.float64, device=self.device) if trace else None
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_forward_points(self._h, n, _ptr(theta), _ptr(nc), k, w.ctypes.data,
+                                        _ptr(amp), _ptr(phase), _ptr(tr), _ptr(status),
+                                        _stream()), "afm_forward_points")
         return {"amp": amp, "phase": phase, "status": status, "trace": tr}
 
     def misfit(self, theta, targets, target_id=None, n_cycles=None):

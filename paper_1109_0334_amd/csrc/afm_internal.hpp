@@ -459,6 +459,8 @@ struct FwdArgs {
     const int32_t *items;      // persistent queue: item order (NULL = plain grid launch)
     int32_t n_items, chunks;   // items = groups x chunks of 64 lanes
     int32_t *head;             // queue head counter (reset to 0 before the launch)
+    double *mtrace;            // optional window modal coordinates, m: [NM][W][mtrace_ld]
+    int64_t mtrace_ld;         // (trajectory fastest)
 };
 
 // Adjoint launch description (see afm_grad_batch).
@@ -526,6 +528,9 @@ struct afm_plan {
     // plan-owned workspace for afm_polish
     void *pws = nullptr;
     size_t pws_bytes = 0;
+    // plan-owned workspace for afm_forward_points (window modal coordinates)
+    void *mws = nullptr;
+    size_t mws_bytes = 0;
     // PSO constants
     double pso_w, pso_c1, pso_c2, pso_vmax;
     // tuned launch shapes of plain forward launches (filled on first use of a batch size)

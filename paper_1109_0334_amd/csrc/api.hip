@@ -220,6 +220,7 @@ afm_status afm_plan_destroy(afm_plan *plan) {
     if (plan->ws) (void)hipFree(plan->ws);
     if (plan->gws) (void)hipFree(plan->gws);
     if (plan->pws) (void)hipFree(plan->pws);
+    if (plan->mws) (void)hipFree(plan->mws);
     if (plan->d_drive_f) (void)hipFree(plan->d_drive_f);
     if (plan->d_drive_d) (void)hipFree(plan->d_drive_d);
     if (plan->d_lock) (void)hipFree(plan->d_lock);
@@ -390,6 +391,7 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
     const size_t bytes = polish_total_bytes(plan, n, kPolishStride);
     if (plan->pws_bytes < bytes) {
         if (plan->pws) (void)hipFree(plan->pws);
+    if (plan->mws) (void)hipFree(plan->mws);
         plan->pws = nullptr;
         plan->pws_bytes = 0;
         if (hipMalloc(&plan->pws, bytes) != hipSuccess)

@@ -74,7 +74,7 @@ __device__ __forceinline__ void integrate(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
     const double (&zc)[T], const KConst &K, int nc, const double *const (&Urow)[T],
     double *const (&trow)[T], const DriveP<typename std::conditional<MIXED, float, double>::type> &dv,
-    LaneOut (&o)[T]) {
+    double *const (&mcol)[T], int64_t mld, LaneOut (&o)[T]) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     static_assert(!DP || T == 1, "a parameter-driven base runs one trajectory per lane");
@@ -199,6 +199,16 @@ __device__ __forceinline__ void integrate(
                         Jd[t] = __builtin_fma(U, U, Jd[t]);
                     }
                     if (trow[t]) trow[t][w0 + s] = u * 1e-9;
+                    if (mcol[t]) {
+                        // modal coordinates (mode 1 from the gap), for deflections elsewhere
+#pragma unroll
+                        for (int i = 0; i < NM; ++i) {
+                            double qi = (double)x[t][i];
+                            if constexpr (COMP) qi -= (double)cx[t][i];
+                            if (i == 0) qi -= zc[t];
+                            mcol[t][((int64_t)i * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                        }
+                    }
                 }
             }
         }
@@ -251,6 +261,7 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
     double zc[T];
     const double *Urow[T];
     double *trow[T];
+    double *mcol[T];
     bool bad[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -270,12 +281,14 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
             Urow[t] = bad[t] ? nullptr : A.targets + row * W;
         }
         trow[t] = (A.trace && act[t]) ? A.trace + i * W : nullptr;
+        mcol[t] = (A.mtrace && act[t]) ? A.mtrace + i : nullptr;
     }
     bool all_bad = true;
 #pragma unroll
     for (int t = 0; t < T; ++t) all_bad = all_bad && bad[t];
     LaneOut o[T];
-    if (!all_bad) integrate<LAW, NM, MIXED, FM, T, DP>(law, zc, K, nc, Urow, trow, dv, o);
+    if (!all_bad)
+        integrate<LAW, NM, MIXED, FM, T, DP>(law, zc, K, nc, Urow, trow, dv, mcol, A.mtrace_ld, o);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         if (!act[t]) continue;
@@ -327,7 +340,8 @@ template <int LAW, int NM, bool MIXED, int FM, bool DP>
 __device__ __forceinline__ LaneOut integrate_mp(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> &law, double zc,
     const KConst &K, int nc, const double *__restrict__ Urow, double *__restrict__ trow, int q,
-    int gbase, const DriveP<typename std::conditional<MIXED, float, double>::type> &dv) {
+    int gbase, const DriveP<typename std::conditional<MIXED, float, double>::type> &dv,
+    double *__restrict__ mcol, int64_t mld) {
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
@@ -424,6 +438,12 @@ __device__ __forceinline__ LaneOut integrate_mp(
                     Jd = __builtin_fma(U, U, Jd);
                 }
                 if (trow && q == 0) trow[w0 + s] = u * 1e-9;
+                if (mcol && q < NM) {  // this lane's modal coordinate (mode 1 from the gap)
+                    double qi = (double)x;
+                    if constexpr (COMP) qi -= (double)cx;
+                    if (q == 0) qi -= zc;
+                    mcol[((int64_t)q * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                }
             };
             if constexpr (DP) {
                 const double jb = 2.0 * ((double)c * N);
@@ -515,7 +535,8 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
             for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
     } else {
         o = integrate_mp<LAW, NM, MIXED, FM, DP>(law, p[0] * 1e9, K, nc, Urow, trow, q, gbase,
-                                                 dv);
+                                                 dv, A.mtrace ? A.mtrace + i : nullptr,
+                                                 A.mtrace_ld);
     }
     if (q == 0) {
         if (A.amp) A.amp[i] = o.A;

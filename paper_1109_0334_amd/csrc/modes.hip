@@ -82,4 +82,21 @@ afm_status afm_beam_modes(int32_t n_modes, int32_t n_points, double E, double I,
     return AFM_OK;
 }
 
+afm_status afm_beam_shapes(int32_t n_modes, int32_t n_x, const double *x, double *w) {
+    using namespace afm;
+    if (n_modes < 1 || n_modes > AFM_MAX_MODES)
+        return fail(AFM_ERR_INVALID, "afm_beam_shapes: n_modes must be in [1, 8]");
+    if (n_x < 0 || (n_x > 0 && (!x || !w)))
+        return fail(AFM_ERR_INVALID, "afm_beam_shapes: x and w are required");
+    for (int k = 0; k < n_x; ++k)
+        if (!(x[k] >= 0.0 && x[k] <= 1.0))
+            return fail(AFM_ERR_INVALID, "afm_beam_shapes: points must lie in [0, 1]");
+    for (int i = 0; i < n_modes; ++i) {
+        const double b = clamped_free_root(i + 1);
+        const double tip = mode_shape(b, 1.0);
+        for (int k = 0; k < n_x; ++k) w[k * n_modes + i] = mode_shape(b, x[k]) / tip;
+    }
+    return AFM_OK;
+}
+
 }  // extern "C"

@@ -98,6 +98,29 @@ def test_gains_against_high_precision_reference(afm):
     np.testing.assert_allclose(a[:3], [1.565984, -0.867872, 0.508851], atol=2e-6)
 
 
+def test_shapes_against_reference_and_oracle(afm, orc):
+    """afm_beam_shapes: tip-normalised shapes at points along the beam equal the textbook
+    hyperbolic form (40 digits) and the oracle's Eq. 6 for the first three modes."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    xs = np.array([0.0, 0.1, 0.25, 0.5, 0.8, 1.0])
+    w = afm.beam_shapes(8, xs)
+    eb = orc.eb_modes(8, 501)
+    for i in range(8):
+        b = mp.findroot(lambda z: mp.cos(z) * mp.cosh(z) + 1, (2 * i + 1) * mp.pi / 2
+                        if i > 0 else mp.mpf("1.875"))
+        sig = (mp.cosh(b) + mp.cos(b)) / (mp.sinh(b) + mp.sin(b))
+        phi = lambda s: mp.cosh(b * s) - mp.cos(b * s) - sig * (mp.sinh(b * s) - mp.sin(b * s))
+        ref = np.array([float(phi(mp.mpf(x)) / phi(mp.mpf(1))) for x in xs])
+        np.testing.assert_allclose(w[:, i], ref, rtol=1e-12, atol=1e-14)
+        if i < 3:
+            L = orc.lib()
+            o = np.array([L.orc_eb_shape(eb["betaL"][i], x) / L.orc_eb_shape(eb["betaL"][i], 1.0)
+                          for x in xs])
+            np.testing.assert_allclose(w[:, i], o, rtol=1e-12, atol=1e-14)
+    assert np.all(w[-1] == 1.0) and np.all(np.abs(w[0]) < 1e-14)
+
+
 @pytest.mark.parametrize("n,npts", [(0, 501), (9, 501), (3, 500), (3, 1)])
 def test_invalid_arguments(afm, n, npts):
     r = (C.c_double * 9)()
