@@ -292,3 +292,21 @@ def test_adjoint_reports_unsupported(afm):
         plan.invert(U, 8, 2, seed=1, lbfgs_steps=2, lbfgs_topk=2)
     out = plan.invert(U, 8, 2, seed=1)  # without the polish the inversion runs
     assert out["best_J"].shape == (1,)
+
+
+def test_mode_count_convergence_matches_oracle(afm, orc):
+    """The paper's mode-count study (Sec. 3.3): the FP64 GPU traces of the beam truncated to
+    1..8 modes give the oracle's relative L2 distances from the eight-mode trace, which fall
+    with the mode count."""
+    tg, to = {}, {}
+    for m in range(1, 9):
+        c = W.mode_convergence(m)
+        plan = afm.Plan(c["model"], c["params"], [], precision="fp64")
+        tg[m] = plan.forward_batch(None, trace=True)["trace"].cpu().numpy()[0]
+        to[m] = orc.forward(c["model"], c["params"], want_trace=True)["trace"]
+        assert np.max(np.abs(tg[m] - to[m])) <= 1e-10 * np.max(np.abs(to[m]))
+    eg = [np.linalg.norm(tg[m] - tg[8]) / np.linalg.norm(tg[8]) for m in range(1, 8)]
+    eo = [np.linalg.norm(to[m] - to[8]) / np.linalg.norm(to[8]) for m in range(1, 8)]
+    print("relative L2 vs 8 modes:", " ".join(f"{e:.2e}" for e in eg))
+    np.testing.assert_allclose(eg, eo, rtol=1e-3)
+    assert all(a > b for a, b in zip(eg[:5], eg[1:6]))

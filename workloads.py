@@ -154,6 +154,20 @@ def paper_inversion(case: str) -> dict:
                 paper=dict(c["paper"]))
 
 
+def mode_convergence(n_modes: int) -> dict:
+    """The paper's mode-count study (Sec. 3.3): the App. A beam truncated to its first n_modes
+    modes, 1000 RK4 steps of 1e-7 s from rest (two periods of a 20 kHz time unit, 500 steps
+    each), App. A's sinusoidal base motion (5 nm at 25.5 kHz), no tip force; the whole trace is
+    compared against the eight-mode one.  Returns dict(model, params)."""
+    eb = beam_modes(8)
+    model = dict(_BEAM, n_modes=n_modes, q=[400.0] * n_modes, ratio=list(eb["ratio"][:n_modes]),
+                 gain=list(eb["gain"][:n_modes]), drive_freq=20e3, steps_per_cycle=500,
+                 n_cycles=2, lockin_cycles=2)
+    p = np.zeros(12)
+    p[8], p[9], p[10] = _APP_A_DRIVE
+    return dict(model=model, params=p)
+
+
 def base_motion(case: str) -> dict:
     """One of the paper's base-motion problems (Sec. 4.1); see paper_inversion."""
     assert case in BASE_MOTION
