@@ -77,6 +77,8 @@ def lib() -> C.CDLL:
         L.orc_forward.argtypes = [mp, dp, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_forward.restype = C.c_int
         L.orc_forward_points.argtypes = [mp, dp, C.c_int32, C.c_int32, dp, dp, dp, dp]
+        L.orc_forward_steady.argtypes = [mp, dp, C.c_int32, C.c_double, dp, dp, dp, dp, dp, ip]
+        L.orc_forward_steady.restype = C.c_int
         L.orc_forward_points.restype = C.c_int
         L.orc_lockin.argtypes = [dp, C.c_int64, C.c_int32, C.c_int64, dp, dp]
         L.orc_misfit.argtypes = [dp, dp, C.c_int64]
@@ -210,6 +212,21 @@ def forward(m: dict, p, target=None, n_cycles=None, want_trace=False):
     st = L.orc_forward(C.byref(mo), _dp(p), nc, _dp(U), C.byref(A), C.byref(phi), C.byref(J),
                        _dp(tr))
     return {"status": st, "A": A.value, "phi": phi.value, "J": J.value, "trace": tr}
+
+
+def forward_steady(m: dict, p, rtol, target=None, n_cycles=None, want_trace=False):
+    """Forward solve with the adaptive steady-state exit: dict(status, A, phi, J, trace,
+    periods); n_cycles (default the model's) is the cap on the periods integrated."""
+    L, mo = lib(), make_model(m)
+    nc = int(m["n_cycles"] if n_cycles is None else n_cycles)
+    U = None if target is None else _f64(target)
+    A, phi, J = C.c_double(), C.c_double(), C.c_double()
+    per = np.zeros(1, np.int32)
+    tr = np.empty(window_len(m)) if want_trace else None
+    st = L.orc_forward_steady(C.byref(mo), _dp(_pv(p)), nc, float(rtol), _dp(U), C.byref(A),
+                              C.byref(phi), C.byref(J), _dp(tr), _ip(per))
+    return {"status": st, "A": A.value, "phi": phi.value, "J": J.value, "trace": tr,
+            "periods": int(per[0])}
 
 
 def forward_points(m: dict, p, weights, n_cycles=None, want_trace=False):

@@ -463,6 +463,62 @@ int orc_forward_points(const orc_model *mo, const double *p, int32_t n_cycles, i
     return st;
 }
 
+/* Forward solve with an adaptive steady-state exit (the uneven-pixel workload's period counts
+ * "until the steady-state tolerance is met"): from the initial condition, period by period,
+ * the one-period lock-in amplitude A_c of period c is compared with the previous period's; the
+ * transient ends after the first period c >= 1 with |A_c - A_{c-1}| < rtol A_c, and at the
+ * latest after n_cycles - lockin periods; the lock-in window is the following lockin periods.
+ * *periods receives the periods integrated (transient + window).  Outputs, health checks and
+ * failure rules as orc_forward (a failed trajectory reports the periods it reached). */
+int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, double rtol,
+                       const double *U, double *A, double *phi, double *J, double *trace,
+                       int32_t *periods) {
+    orc_derived dv;
+    derive(mo, &dv);
+    int m = dv.m, N = mo->steps_per_cycle, L = mo->lockin_cycles;
+    int64_t W = (int64_t)L * N;
+    double y[2 * ORC_MAX_MODES], *u = (double *)malloc(sizeof(double) * N);
+    double *win = (double *)malloc(sizeof(double) * W);
+    orc_initial_state(mo, y);
+    int status = 0, T = n_cycles - L, c = 0;
+    int64_t n = 0;
+    double Aprev = -1.0;
+    for (int k = 0; k < W; k++) win[k] = NAN;
+    for (c = 0; c < T + L && !status; c++) {
+        int in_window = c >= T;
+        for (int s = 0; s < N; s++, n++) {
+            rk4_step(mo, &dv, p, (double)n * dv.h, y);
+            double t = tip(&dv, y);
+            if (in_window) win[(int64_t)(c - T) * N + s] = t;
+            else u[s] = t;
+        }
+        int bad = 0;
+        for (int i = 0; i < 2 * m; i++)
+            if (!isfinite(y[i])) bad = 1;
+        if (bad) status |= ORC_ST_NONFINITE;
+        else if (fabs(tip(&dv, y)) > mo->div_limit * mo->free_amplitude) status |= ORC_ST_DIVERGED;
+        if (status || in_window) continue;
+        double Ac, ph;
+        orc_lockin(u, N, N, 1, &Ac, &ph);
+        if (Aprev > 0.0 && fabs(Ac - Aprev) < rtol * Ac) T = c + 1;
+        Aprev = Ac;
+    }
+    if (periods) *periods = c;
+    if (status == 0) {
+        orc_lockin(win, W, N, 1, A, phi);
+        *J = U ? orc_misfit(U, win, W) : NAN;
+    } else {
+        for (int64_t k = 0; k < W; k++) win[k] = NAN;
+        *A = NAN;
+        *phi = NAN;
+        *J = INFINITY;
+    }
+    if (trace) memcpy(trace, win, sizeof(double) * W);
+    free(u);
+    free(win);
+    return status;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Set-point -> separation (AFM amplitude feedback, Sec. 1)                                   */
 /* ------------------------------------------------------------------------------------------ */
