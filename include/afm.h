@@ -132,7 +132,19 @@ typedef struct afm_problem {
     double pso_w, pso_c1, pso_c2, pso_vmax; /* Eq. 8 weights; 0 => 0.7298, 1.49618, 1.49618, 1 */
     int32_t polish_precision; /* arithmetic of afm_polish and the invert polish: AFM_POLISH_*   */
     int32_t drive_mode;       /* AFM_DRIVE_* (0 = TABLE)                                       */
+    double steady_rtol;       /* > 0: adaptive steady-state exit (below); 0 = off              */
 } afm_problem;
+
+/* Adaptive steady-state exit (steady_rtol > 0; TABLE drive only): each trajectory integrates
+ * period by period; after every period before its window it takes that period's lock-in
+ * amplitude A_c (the X, Y projection over the period's N samples) and, from the second period
+ * on, ends its transient after the first period with |A_c - A_{c-1}| < steady_rtol A_c; its
+ * lock-in window is then the following lockin_cycles periods.  The period count (problem or
+ * per trajectory) stays the cap: without such a period the window is its last lockin_cycles
+ * periods, as without the exit.  Applies to every forward solve (afm_forward_batch, afm_misfit,
+ * afm_forward_points, afm_invert, one trajectory per lane); afm_forward_steady reports the
+ * periods each trajectory integrated.  The adjoint is not built for it (afm_grad_batch,
+ * afm_polish and the invert polish return AFM_ERR_UNSUPPORTED). */
 
 /* Polish arithmetic: the plan's own precision, or FP32 (mixed) / FP64 adjoint and misfits. */
 enum { AFM_POLISH_PLAN = 0, AFM_POLISH_MIXED = 1, AFM_POLISH_FP64 = 2 };
@@ -186,6 +198,13 @@ afm_status afm_set_launch_shape(afm_plan *plan, int32_t block, int32_t tpl);
 afm_status afm_forward_batch(afm_plan *plan, int64_t n, const double *theta,
                              const int32_t *n_cycles, double *amp, double *phase, double *trace,
                              int32_t *status, afm_stream_t stream);
+
+/* afm_forward_batch that also writes periods [n] (device): the drive periods each trajectory
+ * integrated -- transient plus window with the adaptive steady-state exit, the period count
+ * without it, the periods up to a failure, 0 for a bad input.  periods is required. */
+afm_status afm_forward_steady(afm_plan *plan, int64_t n, const double *theta,
+                              const int32_t *n_cycles, double *amp, double *phase, double *trace,
+                              int32_t *status, int32_t *periods, afm_stream_t stream);
 
 /* Deflection at points along the beam for n parameter points (the paper's deflection points,
  * n_dp, Sec. 3.2): u(x_k, t) = sum_i w[k][i] q_i(t) over the tip-normalised modal coordinates

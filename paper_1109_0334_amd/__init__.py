@@ -42,7 +42,7 @@ ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
            "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-           "afm_forward_points", "afm_beam_modes", "afm_beam_shapes", "afm_last_error",
+           "afm_forward_steady", "afm_forward_points", "afm_beam_modes", "afm_beam_shapes", "afm_last_error",
            "afm_version")
 
 
@@ -63,6 +63,7 @@ class _Problem(C.Structure):
         ("hi", C.c_double * MAX_PARAMS), ("log_scale", C.c_int32 * MAX_PARAMS),
         ("pso_w", C.c_double), ("pso_c1", C.c_double), ("pso_c2", C.c_double),
         ("pso_vmax", C.c_double), ("polish_precision", C.c_int32), ("drive_mode", C.c_int32),
+        ("steady_rtol", C.c_double),
     ]
 
 
@@ -100,11 +101,12 @@ def lib() -> C.CDLL:
     L.afm_beam_modes.argtypes = [i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp]
     L.afm_beam_shapes.argtypes = [i32, i32, vp, vp]
     L.afm_forward_points.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    L.afm_forward_steady.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
               "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-              "afm_beam_modes", "afm_beam_shapes", "afm_forward_points"):
+              "afm_beam_modes", "afm_beam_shapes", "afm_forward_points", "afm_forward_steady"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -146,6 +148,7 @@ def make_problem(model: dict, params, free=(), pso=None, polish="plan") -> _Prob
     p.ic = IC[ic] if isinstance(ic, str) else int(ic)
     drive = model.get("drive", "table")
     p.drive_mode = DRIVE[drive] if isinstance(drive, str) else int(drive)
+    p.steady_rtol = float(model.get("steady_rtol", 0.0))
     p.n_modes = int(model.get("n_modes", 1))
     p.steps_per_cycle = int(model["steps_per_cycle"])
     p.n_cycles = int(model["n_cycles"])
@@ -271,6 +274,24 @@ class Plan:
         _check(lib().afm_forward_batch(self._h, n, _ptr(theta), _ptr(nc), _ptr(amp), _ptr(phase),
                                        _ptr(tr), _ptr(status), _stream()), "afm_forward_batch")
         return {"amp": amp, "phase": phase, "status": status, "trace": tr}
+
+    def forward_steady(self, theta, n_cycles=None, trace=False):
+        """forward_batch plus the periods each trajectory integrated (afm_forward_steady)."""
+        import torch
+
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, -1) if self.n_free else \
+            torch.empty(0, 1, dtype=torch.float64, device=self.device)
+        n = theta.shape[1]
+        amp = torch.empty(n, dtype=torch.float64, device=self.device)
+        phase = torch.empty_like(amp)
+        status = torch.empty(n, dtype=torch.int32, device=self.device)
+        periods = torch.empty(n, dtype=torch.int32, device=self.device)
+        tr = torch.empty(n, self.W, dtype=torch.float64, device=self.device) if trace else None
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_forward_steady(self._h, n, _ptr(theta), _ptr(nc), _ptr(amp), _ptr(phase),
+                                        _ptr(tr), _ptr(status), _ptr(periods), _stream()),
+               "afm_forward_steady")
+        return {"amp": amp, "phase": phase, "status": status, "periods": periods, "trace": tr}
 
     def forward_points(self, theta, weights, n_cycles=None, trace=False):
         """Deflection at points along the beam: weights [n_points][n_modes] (host) ->

@@ -42,6 +42,7 @@ struct KConst {
     double k;              // first-mode stiffness, N/m
     double wd;             // drive angular frequency, rad/s
     double fref;           // drive frequency, Hz (the time unit of a parameter-driven base)
+    double steady_rtol;    // > 0: adaptive steady-state exit (per-period amplitude change)
     double G;              // (w0 / wd)^2
     double h;              // 2 pi / N
     double div_nm;         // divergence threshold on |u|, nm
@@ -461,6 +462,7 @@ struct FwdArgs {
     int32_t *head;             // queue head counter (reset to 0 before the launch)
     double *mtrace;            // optional window modal coordinates, m: [NM][W][mtrace_ld]
     int64_t mtrace_ld;         // (trajectory fastest)
+    int32_t *periods;          // optional periods integrated per trajectory
 };
 
 // Adjoint launch description (see afm_grad_batch).

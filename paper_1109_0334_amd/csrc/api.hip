@@ -65,6 +65,10 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     const bool dparams = pr.drive_mode == AFM_DRIVE_PARAMS;
     if (dparams && pr.ic != AFM_IC_REST)
         return fail(AFM_ERR_INVALID, "a parameter-driven base motion needs ic = AFM_IC_REST");
+    if (!(pr.steady_rtol >= 0.0) || !std::isfinite(pr.steady_rtol))
+        return fail(AFM_ERR_INVALID, "steady_rtol must be finite and >= 0");
+    if (pr.steady_rtol > 0.0 && dparams)
+        return fail(AFM_ERR_INVALID, "the steady-state exit needs the periodic drive table");
     const int np = kLawParams[pr.law];
     // a slot a trajectory reads: the law's, and with PARAMS the base motion's (8 .. 10)
     auto used = [&](int q) { return (q >= 0 && q < np) || (dparams && q >= AFM_P_BASE_A && q <= AFM_P_BASE_G); };
@@ -88,6 +92,7 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     K.lockin = pr.lockin_cycles;
     K.n_free = pr.n_free;
     K.drive_mode = pr.drive_mode;
+    K.steady_rtol = pr.steady_rtol;
     K.fref = pr.drive_freq;
     for (int j = 0; j < kMaxParams; ++j) {
         K.free_index[j] = j < pr.n_free ? pr.free_index[j] : -1;
@@ -250,6 +255,27 @@ afm_status afm_forward_batch(afm_plan *plan, int64_t n, const double *theta,
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_forward_batch launch");
 }
 
+afm_status afm_forward_steady(afm_plan *plan, int64_t n, const double *theta,
+                              const int32_t *n_cycles, double *amp, double *phase, double *trace,
+                              int32_t *status, int32_t *periods, afm_stream_t stream) {
+    afm_status st = check_forward_args(plan, n, theta);
+    if (st != AFM_OK) return st;
+    if (n > 0 && (!amp || !phase || !status || !periods))
+        return fail(AFM_ERR_INVALID, "amp, phase, status and periods are required");
+    FwdArgs a{};
+    a.n = n;
+    a.ld = n;
+    a.theta = theta;
+    a.n_cycles = n_cycles;
+    a.amp = amp;
+    a.phase = phase;
+    a.trace = trace;
+    a.status = status;
+    a.periods = periods;
+    hipError_t e = launch_forward(plan, a, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_forward_steady launch");
+}
+
 afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
                       const int32_t *target_id, const double *targets, int32_t n_targets,
                       double *J, int32_t *status, afm_stream_t stream) {
@@ -322,6 +348,8 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     if (ckpt_stride < 0) return fail(AFM_ERR_INVALID, "ckpt_stride < 0");
     if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
         return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
+    if (plan->kc.steady_rtol > 0.0)
+        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of the adaptive steady-state exit is not built");
     if (n == 0) return AFM_OK;
     GradArgs a{};
     a.n = n;
@@ -385,6 +413,8 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
     if (plan->prob.n_free < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
     if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
         return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
+    if (plan->kc.steady_rtol > 0.0)
+        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of the adaptive steady-state exit is not built");
     if (n == 0) return AFM_OK;
     if (!z || !targets || !J) return fail(AFM_ERR_INVALID, "z, targets and J are required");
     if (n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");

@@ -27,6 +27,7 @@ namespace {
 struct LaneOut {
     double A, phi, J;
     int32_t st;
+    int32_t used;  // periods integrated (transient + window, or up to a failure)
 };
 
 // Base motion from a trajectory's own parameters: the chirp of Eq. 10 (g = 0 gives Eq. 9), with
@@ -68,8 +69,11 @@ struct DriveP {
 // instruction streams the scheduler interleaves) and share the drive-table loads; a trajectory
 // that fails keeps being stepped (its results are discarded) until all have failed.  DP: the
 // drive comes from the trajectory's own base-motion parameters (dv) instead of the table (one
-// trajectory per lane).
-template <int LAW, int NM, bool MIXED, int FM, int T, bool DP>
+// trajectory per lane).  EX: adaptive steady-state exit (one trajectory per lane): after every
+// transient period the lane compares that period's lock-in amplitude with the previous one's and,
+// once they differ by less than K.steady_rtol relative, starts its window with the next period
+// (nc stays the cap).
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP, bool EX>
 __device__ __forceinline__ void integrate(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
     const double (&zc)[T], const KConst &K, int nc, const double *const (&Urow)[T],
@@ -78,6 +82,7 @@ __device__ __forceinline__ void integrate(
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     static_assert(!DP || T == 1, "a parameter-driven base runs one trajectory per lane");
+    static_assert(!EX || (T == 1 && !DP), "the adaptive exit runs one trajectory per lane");
     const R *__restrict__ Dt;
     if constexpr (MIXED) Dt = K.drive_f;
     else Dt = K.drive_d;
@@ -100,20 +105,58 @@ __device__ __forceinline__ void integrate(
     }
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     const int N = K.N;
-    const int c_win = nc - K.lockin;
+    int c_win = nc - K.lockin;  // first window period (EX: moves up once the amplitude settles)
     const double lim = K.div_nm;
     double Sc[T], Ss[T], Jn[T], Jd[T];
-    int32_t st[T];
+    int32_t st[T], used[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         Sc[t] = Ss[t] = Jn[t] = Jd[t] = 0.0;
         st[t] = 0;
+        used[t] = 0;
     }
     R Dc = R(0);  // DP: drive term at the start of the next step
     if constexpr (DP) Dc = dv.at(0.0);
+    double Aprev = -1.0;  // EX: previous transient period's lock-in amplitude
 
-    for (int c = 0; c < nc; ++c) {
-        if (DP && c < c_win) {
+    for (int c = 0; c < c_win + K.lockin; ++c) {
+        if (EX && c < c_win) {
+            // transient period with the one-period lock-in of the deflection
+            double Pc = 0.0, Ps = 0.0;
+            auto tsum = [&](int s) {
+                const double u = sample<NM, COMP>(x[0], cx[0], zc[0]);
+                Pc = __builtin_fma(u, Lc[s + 1], Pc);
+                Ps = __builtin_fma(u, Ls[s + 1], Ps);
+            };
+            int s = 0;
+            for (; s + 4 <= N; s += 4) {
+                using CR = const __attribute__((address_space(4))) R;
+                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
+                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       e0, e1, e2);
+                tsum(s);
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       e2, e3, e4);
+                tsum(s + 1);
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       e4, e5, e6);
+                tsum(s + 2);
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       e6, e7, e8);
+                tsum(s + 3);
+            }
+            for (; s < N; ++s) {
+                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                                       Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
+                tsum(s);
+            }
+            const double X = 2.0 * Pc / N, Y = 2.0 * Ps / N;
+            const double A = ::sqrt(__builtin_fma(X, X, Y * Y));
+            if (Aprev > 0.0 && fabs(A - Aprev) < K.steady_rtol * A) c_win = c + 1;
+            Aprev = A;
+        } else if (DP && c < c_win) {
             const double jb = 2.0 * ((double)c * N);
             for (int s = 0; s < N; ++s) {
                 const double j = jb + 2.0 * s;
@@ -222,6 +265,7 @@ __device__ __forceinline__ void integrate(
                 for (int i = 0; i < NM; ++i) fin = fin && isfinite(x[t][i]) && isfinite(v[t][i]);
                 if (!fin) st[t] = AFM_ST_NONFINITE;
                 else if (fabs(sample<NM, COMP>(x[t], cx[t], zc[t])) > lim) st[t] = AFM_ST_DIVERGED;
+                if (st[t]) used[t] = c + 1;
             }
             alive = alive || !st[t];
         }
@@ -230,6 +274,7 @@ __device__ __forceinline__ void integrate(
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         o[t].st = st[t];
+        o[t].used = st[t] ? used[t] : c_win + K.lockin;
         if (st[t]) {
             o[t].A = NAN;
             o[t].phi = NAN;
@@ -250,7 +295,7 @@ __device__ __forceinline__ void integrate(
 // One lane's T trajectories ii[t] (those with act[t] false only keep the lane's time loop
 // company and write nothing): parameter load, bounds checks, integration, outputs.  All T
 // trajectories run nc periods.
-template <int LAW, int NM, bool MIXED, int FM, int T, bool DP>
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP, bool EX>
 __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
                                              const int64_t (&ii)[T], const bool (&act)[T],
                                              int nc) {
@@ -288,7 +333,8 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
     for (int t = 0; t < T; ++t) all_bad = all_bad && bad[t];
     LaneOut o[T];
     if (!all_bad)
-        integrate<LAW, NM, MIXED, FM, T, DP>(law, zc, K, nc, Urow, trow, dv, mcol, A.mtrace_ld, o);
+        integrate<LAW, NM, MIXED, FM, T, DP, EX>(law, zc, K, nc, Urow, trow, dv, mcol,
+                                                 A.mtrace_ld, o);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         if (!act[t]) continue;
@@ -297,10 +343,12 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
             o[t].phi = NAN;
             o[t].J = INFINITY;
             o[t].st = AFM_ST_BAD_INPUT;
+            o[t].used = 0;
             if (trow[t])
                 for (int64_t w = 0; w < W; ++w) trow[t][w] = NAN;
         }
         const int64_t i = ii[t];
+        if (A.periods) A.periods[i] = o[t].used;
         if (A.amp) A.amp[i] = o[t].A;
         if (A.phase) A.phase[i] = o[t].phi;
         if (A.J) A.J[i] = o[t].J;
@@ -311,7 +359,7 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
 // T trajectories per lane: lane l of block b owns b B T + t B + l, t < T (coalesced per t).
 // With T > 1 the period count must be the plan's (no per-trajectory counts).  DP: the
 // parameter-driven base motion (T = 1).
-template <int LAW, int NM, bool MIXED, int FM, int T, bool DP = false>
+template <int LAW, int NM, bool MIXED, int FM, int T, bool DP = false, bool EX = false>
 __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * T + threadIdx.x;
     if (i0 >= A.n) return;
@@ -327,7 +375,7 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
         const int64_t grp = A.group > 0 ? i0 / A.group : i0;
         if (A.n_cycles) nc = A.n_cycles[grp];
     }
-    lane_forward<LAW, NM, MIXED, FM, T, DP>(A, K, ii, act, nc);
+    lane_forward<LAW, NM, MIXED, FM, T, DP, EX>(A, K, ii, act, nc);
 }
 
 // Mode-parallel forward: G lanes per trajectory (G = 2 for two modes, 4 for three or four, 8 for
@@ -370,7 +418,7 @@ __device__ __forceinline__ LaneOut integrate_mp(
     const int c_win = nc - K.lockin;
     const double lim = K.div_nm;
     double Sc = 0.0, Ss = 0.0, Jn = 0.0, Jd = 0.0;
-    int32_t st = 0;
+    int32_t st = 0, used = 0;
     R Dc = R(0);  // DP: drive term at the start of the next step
     if constexpr (DP) Dc = dv.at(0.0);
     // DP: the eight new drive terms of four steps (half-steps j0 .. j0 + 7), evaluated 8 / G per
@@ -473,15 +521,18 @@ __device__ __forceinline__ LaneOut integrate_mp(
         if constexpr (G == 8) nonfinite |= __shfl_xor(nonfinite, 4, 64);
         if (nonfinite) {
             st = AFM_ST_NONFINITE;
+            used = c + 1;
             break;
         }
         if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > lim) {
             st = AFM_ST_DIVERGED;
+            used = c + 1;
             break;
         }
     }
     LaneOut o;
     o.st = st;
+    o.used = st ? used : nc;
     if (st) {
         o.A = NAN;
         o.phi = NAN;
@@ -531,6 +582,7 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
         o.phi = NAN;
         o.J = INFINITY;
         o.st = AFM_ST_BAD_INPUT;
+        o.used = 0;
         if (trow && q == 0)
             for (int64_t w = 0; w < W; ++w) trow[w] = NAN;
     } else {
@@ -543,6 +595,7 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
         if (A.phase) A.phase[i] = o.phi;
         if (A.J) A.J[i] = o.J;
         if (A.status) A.status[i] = o.st;
+        if (A.periods) A.periods[i] = o.used;
     }
 }
 
@@ -551,7 +604,7 @@ __global__ void __launch_bounds__(256) k_forward_mp(const FwdArgs A, const KCons
 // queue ordered longest first, until the queue is empty; every wave reaches the exit.  The
 // group's period count is the same for all lanes of an item, so it is moved to a scalar
 // register and the time loops run as uniform scalar loops.
-template <int LAW, int NM, bool MIXED, int FM>
+template <int LAW, int NM, bool MIXED, int FM, bool EX = false>
 __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KConst K) {
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -567,7 +620,7 @@ __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KC
         if (local < A.group) {
             const int64_t ii[1] = {grp * A.group + local};
             const bool act[1] = {true};
-            lane_forward<LAW, NM, MIXED, FM, 1, false>(A, K, ii, act, nc);
+            lane_forward<LAW, NM, MIXED, FM, 1, false, EX>(A, K, ii, act, nc);
         }
     }
 }
@@ -633,6 +686,22 @@ hipError_t launch_dp(const FwdArgs &a, const KConst &K, FwdShape sh, hipStream_t
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
+    if (K.steady_rtol > 0.0) {
+        // adaptive steady-state exit: one trajectory per lane (each lane leaves its transient
+        // when its own amplitude settles), not tuned; the work queue keeps its longest-first
+        // order and its wave-uniform contact skip
+        if (a.items) {
+            hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
+            const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
+            hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree, true>),
+                               dim3(blocks), dim3(256), 0, s, a, K);
+            return hipGetLastError();
+        }
+        const int block = a.n < kSmallBatch ? 64 : 256;
+        hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmFree, 1, false, true>),
+                           dim3((unsigned)((a.n + block - 1) / block)), dim3(block), 0, s, a, K);
+        return hipGetLastError();
+    }
     if (K.drive_mode != AFM_DRIVE_TABLE) {
         // parameter-driven base: one trajectory per lane or one lane per mode, tuned like the
         // fixed-drive shapes; a work-queue batch runs as a plain grid (per-group period counts

@@ -45,11 +45,11 @@ _LAYOUT_PROBE = r"""
 #include <stdio.h>
 #include "afm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(afm_problem), offsetof(afm_problem, k),
          offsetof(afm_problem, params), offsetof(afm_problem, n_free),
          offsetof(afm_problem, lo), offsetof(afm_problem, pso_w),
          offsetof(afm_problem, polish_precision), offsetof(afm_problem, drive_mode),
-         sizeof(afm_swarm));
+         offsetof(afm_problem, steady_rtol), sizeof(afm_swarm));
   printf("%zu %zu\n", offsetof(afm_swarm, z), offsetof(afm_swarm, theta));
   return 0;
 }
@@ -67,7 +67,8 @@ def test_binding_struct_layout_matches_header(afm, tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     P, S = afm._Problem, afm._Swarm
     expect = [C.sizeof(P), P.k.offset, P.params.offset, P.n_free.offset, P.lo.offset,
-              P.pso_w.offset, P.polish_precision.offset, P.drive_mode.offset, C.sizeof(S),
+              P.pso_w.offset, P.polish_precision.offset, P.drive_mode.offset,
+              P.steady_rtol.offset, C.sizeof(S),
               S.z.offset, S.theta.offset]
     assert [int(x) for x in out] == expect
 
@@ -82,7 +83,9 @@ def _base_model():
     dict(n_modes=0), dict(n_modes=9), dict(law=9), dict(steps_per_cycle=3),
     dict(steps_per_cycle=5000), dict(lockin_cycles=0), dict(n_cycles=1, lockin_cycles=2),
     dict(k=0.0), dict(free_amplitude=-1.0), dict(q=[0.0]), dict(ic=7), dict(drive=3),
-    dict(drive="params")])  # a parameter-driven base needs ic = rest
+    dict(drive="params"),  # a parameter-driven base needs ic = rest
+    dict(steady_rtol=-1.0), dict(steady_rtol=float("nan")),
+    dict(drive="params", ic="rest", steady_rtol=1e-6)])  # a chirp has no steady state
 def test_invalid_problem_rejected_before_hip(afm, bad):
     m = dict(_base_model(), **bad)
     prob = afm.make_problem(m, [14e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9], [(1, 1e-20, 1e-19, 0)])
