@@ -211,49 +211,62 @@ __device__ __forceinline__ void integrate(
                 Un[t] = Up[t] ? Up[t][0] : 0.0;
             }
             const double jb = 2.0 * ((double)c * N);
-            for (int s = 0; s < N; ++s) {
-                const double lc = Lc[s + 1], ls = Ls[s + 1];
-                R D0, D1, D2;
-                if constexpr (DP) {
-                    D0 = Dc;
-                    D1 = dv.at(jb + 2.0 * s + 1.0);
-                    D2 = dv.at(jb + 2.0 * s + 2.0);
-                    Dc = D2;
-                } else {
-                    D0 = Dt[2 * s];
-                    D1 = Dt[2 * s + 1];
-                    D2 = Dt[2 * s + 2];
-                }
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const double Uc = Un[t];
-                    if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
-                    rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h, h2,
-                                           h6, D0, D1, D2);
-                    // explicit fmas: with contraction left to the compiler, instantiations
-                    // that differ only in lanes per trajectory could round differently
-                    const double u = sample<NM, COMP>(x[t], cx[t], zc[t]);
-                    Sc[t] = __builtin_fma(u, lc, Sc[t]);
-                    Ss[t] = __builtin_fma(u, ls, Ss[t]);
-                    if (Up[t]) {
-                        const double U = Uc * 1e9;
-                        const double e = U - u;
-                        Jn[t] = __builtin_fma(e, e, Jn[t]);
-                        Jd[t] = __builtin_fma(U, U, Jd[t]);
+            // the window loop is instantiated with and without the trace / modal-coordinate
+            // stores, so that the common case (misfits only) has no store branches in it
+            auto window = [&](auto out_tag) {
+                constexpr bool OUT = decltype(out_tag)::value;
+                for (int s = 0; s < N; ++s) {
+                    const double lc = Lc[s + 1], ls = Ls[s + 1];
+                    R D0, D1, D2;
+                    if constexpr (DP) {
+                        D0 = Dc;
+                        D1 = dv.at(jb + 2.0 * s + 1.0);
+                        D2 = dv.at(jb + 2.0 * s + 2.0);
+                        Dc = D2;
+                    } else {
+                        D0 = Dt[2 * s];
+                        D1 = Dt[2 * s + 1];
+                        D2 = Dt[2 * s + 2];
                     }
-                    if (trow[t]) trow[t][w0 + s] = u * 1e-9;
-                    if (mcol[t]) {
-                        // modal coordinates (mode 1 from the gap), for deflections elsewhere
 #pragma unroll
-                        for (int i = 0; i < NM; ++i) {
-                            double qi = (double)x[t][i];
-                            if constexpr (COMP) qi -= (double)cx[t][i];
-                            if (i == 0) qi -= zc[t];
-                            mcol[t][((int64_t)i * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                    for (int t = 0; t < T; ++t) {
+                        const double Uc = Un[t];
+                        if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
+                        rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
+                                               h2, h6, D0, D1, D2);
+                        // explicit fmas: with contraction left to the compiler, instantiations
+                        // that differ only in lanes per trajectory could round differently
+                        const double u = sample<NM, COMP>(x[t], cx[t], zc[t]);
+                        Sc[t] = __builtin_fma(u, lc, Sc[t]);
+                        Ss[t] = __builtin_fma(u, ls, Ss[t]);
+                        if (Up[t]) {
+                            const double U = Uc * 1e9;
+                            const double e = U - u;
+                            Jn[t] = __builtin_fma(e, e, Jn[t]);
+                            Jd[t] = __builtin_fma(U, U, Jd[t]);
+                        }
+                        if constexpr (OUT) {
+                            if (trow[t]) trow[t][w0 + s] = u * 1e-9;
+                            if (mcol[t]) {
+                                // modal coordinates (mode 1 from the gap), for deflections
+                                // elsewhere
+#pragma unroll
+                                for (int i = 0; i < NM; ++i) {
+                                    double qi = (double)x[t][i];
+                                    if constexpr (COMP) qi -= (double)cx[t][i];
+                                    if (i == 0) qi -= zc[t];
+                                    mcol[t][((int64_t)i * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                                }
+                            }
                         }
                     }
                 }
-            }
+            };
+            bool out = false;
+#pragma unroll
+            for (int t = 0; t < T; ++t) out = out || trow[t] || mcol[t];
+            if (out) window(std::true_type{});
+            else window(std::false_type{});
         }
         // end-of-period health check: every state entry finite and |u| within the limit
         bool alive = false;
@@ -471,8 +484,11 @@ __device__ __forceinline__ LaneOut integrate_mp(
             const int w0 = (c - c_win) * N;
             const double *__restrict__ Up = Urow ? Urow + w0 : nullptr;
             double Un = Up ? Up[0] : 0.0;
-            // one window step: RK4, sample, lock-in and misfit sums, trace
-            auto wstep = [&](int s, R D0, R D1, R D2) {
+            // one window step: RK4, sample, lock-in and misfit sums, and (OUT) the trace and
+            // modal-coordinate stores; the loops are instantiated with and without the stores so
+            // that the common case (misfits only) has no store branches in them
+            auto wstep = [&](auto out_tag, int s, R D0, R D1, R D2) {
+                constexpr bool OUT = decltype(out_tag)::value;
                 const double Uc = Un;
                 if (Up) Un = Up[s + 1 < N ? s + 1 : s];
                 rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, D0, D1, D2);
@@ -485,34 +501,41 @@ __device__ __forceinline__ LaneOut integrate_mp(
                     Jn = __builtin_fma(e, e, Jn);
                     Jd = __builtin_fma(U, U, Jd);
                 }
-                if (trow && q == 0) trow[w0 + s] = u * 1e-9;
-                if (mcol && q < NM) {  // this lane's modal coordinate (mode 1 from the gap)
-                    double qi = (double)x;
-                    if constexpr (COMP) qi -= (double)cx;
-                    if (q == 0) qi -= zc;
-                    mcol[((int64_t)q * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                if constexpr (OUT) {
+                    if (trow && q == 0) trow[w0 + s] = u * 1e-9;
+                    if (mcol && q < NM) {  // this lane's modal coordinate (mode 1 from the gap)
+                        double qi = (double)x;
+                        if constexpr (COMP) qi -= (double)cx;
+                        if (q == 0) qi -= zc;
+                        mcol[((int64_t)q * K.lockin * N + w0 + s) * mld] = qi * 1e-9;
+                    }
                 }
             };
-            if constexpr (DP) {
-                const double jb = 2.0 * ((double)c * N);
-                int s = 0;
-                for (; s + 4 <= N; s += 4) {
-                    R d[8];
-                    drive8(jb + 2.0 * s + 1.0, d);
-                    wstep(s, Dc, d[0], d[1]);
-                    wstep(s + 1, d[1], d[2], d[3]);
-                    wstep(s + 2, d[3], d[4], d[5]);
-                    wstep(s + 3, d[5], d[6], d[7]);
-                    Dc = d[7];
+            auto window = [&](auto out_tag) {
+                if constexpr (DP) {
+                    const double jb = 2.0 * ((double)c * N);
+                    int s = 0;
+                    for (; s + 4 <= N; s += 4) {
+                        R d[8];
+                        drive8(jb + 2.0 * s + 1.0, d);
+                        wstep(out_tag, s, Dc, d[0], d[1]);
+                        wstep(out_tag, s + 1, d[1], d[2], d[3]);
+                        wstep(out_tag, s + 2, d[3], d[4], d[5]);
+                        wstep(out_tag, s + 3, d[5], d[6], d[7]);
+                        Dc = d[7];
+                    }
+                    for (; s < N; ++s) {
+                        const R D1 = dv.at(jb + 2.0 * s + 1.0), D2 = dv.at(jb + 2.0 * s + 2.0);
+                        wstep(out_tag, s, Dc, D1, D2);
+                        Dc = D2;
+                    }
+                } else {
+                    for (int s = 0; s < N; ++s)
+                        wstep(out_tag, s, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
                 }
-                for (; s < N; ++s) {
-                    const R D1 = dv.at(jb + 2.0 * s + 1.0), D2 = dv.at(jb + 2.0 * s + 2.0);
-                    wstep(s, Dc, D1, D2);
-                    Dc = D2;
-                }
-            } else {
-                for (int s = 0; s < N; ++s) wstep(s, Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
-            }
+            };
+            if (trow || mcol) window(std::true_type{});
+            else window(std::false_type{});
         }
         // end-of-period health check, combined over the group
         int nonfinite = !(isfinite(x) && isfinite(v));
