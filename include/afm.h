@@ -136,15 +136,17 @@ typedef struct afm_problem {
 } afm_problem;
 
 /* Adaptive steady-state exit (steady_rtol > 0; TABLE drive only): each trajectory integrates
- * period by period; after every period before its window it takes that period's lock-in
- * amplitude A_c (the X, Y projection over the period's N samples) and, from the second period
- * on, ends its transient after the first period with |A_c - A_{c-1}| < steady_rtol A_c; its
- * lock-in window is then the following lockin_cycles periods.  The period count (problem or
- * per trajectory) stays the cap: without such a period the window is its last lockin_cycles
- * periods, as without the exit.  Applies to every forward solve (afm_forward_batch, afm_misfit,
- * afm_forward_points, afm_invert, one trajectory per lane); afm_forward_steady reports the
- * periods each trajectory integrated.  The adjoint is not built for it (afm_grad_batch,
- * afm_polish and the invert polish return AFM_ERR_UNSUPPORTED). */
+ * period by period; at the end of every period before its window it takes the stroboscopic point
+ * P = (u, u'/wd) -- deflection and rate at the same drive phase each time; |P| is the amplitude
+ * of a steady sinusoid -- and ends its transient after the first period with
+ * |P_c - P_{c-1}| < steady_rtol |P_c| (P_{-1}: the initial state); its lock-in window is then the
+ * following lockin_cycles periods.  The period count (problem or per trajectory) stays the cap:
+ * without such a period the window is its last lockin_cycles periods, as without the exit.
+ * Applies to every forward solve (afm_forward_batch, afm_misfit, afm_forward_points, afm_invert;
+ * one trajectory per lane; work-queue batches of afm_invert refill each lane with the next
+ * trajectory as its own ends); afm_forward_steady reports the periods each trajectory
+ * integrated.  The adjoint is not built for it (afm_grad_batch, afm_polish and the invert polish
+ * return AFM_ERR_UNSUPPORTED). */
 
 /* Polish arithmetic: the plan's own precision, or FP32 (mixed) / FP64 adjoint and misfits. */
 enum { AFM_POLISH_PLAN = 0, AFM_POLISH_MIXED = 1, AFM_POLISH_FP64 = 2 };

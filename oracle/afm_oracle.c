@@ -464,12 +464,22 @@ int orc_forward_points(const orc_model *mo, const double *p, int32_t n_cycles, i
 }
 
 /* Forward solve with an adaptive steady-state exit (the uneven-pixel workload's period counts
- * "until the steady-state tolerance is met"): from the initial condition, period by period,
- * the one-period lock-in amplitude A_c of period c is compared with the previous period's; the
- * transient ends after the first period c >= 1 with |A_c - A_{c-1}| < rtol A_c, and at the
- * latest after n_cycles - lockin periods; the lock-in window is the following lockin periods.
- * *periods receives the periods integrated (transient + window).  Outputs, health checks and
- * failure rules as orc_forward (a failed trajectory reports the periods it reached). */
+ * "until the steady-state tolerance is met"): from the initial condition, period by period, the
+ * stroboscopic point of the orbit -- deflection u and rate u' / wd at the end of each period,
+ * the same drive phase every time -- is compared with the previous period's (the initial state
+ * before the first period): the transient ends after the first period c with
+ * |P_c - P_{c-1}| < rtol |P_c|, P = (u, u' / wd) (for a steady sinusoid |P| is its amplitude, and
+ * the change covers amplitude and phase), and at the latest after n_cycles - lockin periods; the
+ * lock-in window is the following lockin periods.  *periods receives the periods integrated
+ * (transient + window).  Outputs, health checks and failure rules as orc_forward (a failed
+ * trajectory reports the periods it reached). */
+static void strobe(const orc_derived *dv, const double *y, double *P) {
+    double ud = 0.0;
+    for (int i = 0; i < dv->m; i++) ud += y[dv->m + i];
+    P[0] = tip(dv, y);
+    P[1] = ud / dv->wd;
+}
+
 int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, double rtol,
                        const double *U, double *A, double *phi, double *J, double *trace,
                        int32_t *periods) {
@@ -477,20 +487,18 @@ int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, d
     derive(mo, &dv);
     int m = dv.m, N = mo->steps_per_cycle, L = mo->lockin_cycles;
     int64_t W = (int64_t)L * N;
-    double y[2 * ORC_MAX_MODES], *u = (double *)malloc(sizeof(double) * N);
-    double *win = (double *)malloc(sizeof(double) * W);
+    double y[2 * ORC_MAX_MODES], *win = (double *)malloc(sizeof(double) * W);
     orc_initial_state(mo, y);
     int status = 0, T = n_cycles - L, c = 0;
     int64_t n = 0;
-    double Aprev = -1.0;
+    double Pprev[2], P[2];
+    strobe(&dv, y, Pprev);
     for (int k = 0; k < W; k++) win[k] = NAN;
     for (c = 0; c < T + L && !status; c++) {
         int in_window = c >= T;
         for (int s = 0; s < N; s++, n++) {
             rk4_step(mo, &dv, p, (double)n * dv.h, y);
-            double t = tip(&dv, y);
-            if (in_window) win[(int64_t)(c - T) * N + s] = t;
-            else u[s] = t;
+            if (in_window) win[(int64_t)(c - T) * N + s] = tip(&dv, y);
         }
         int bad = 0;
         for (int i = 0; i < 2 * m; i++)
@@ -498,10 +506,10 @@ int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, d
         if (bad) status |= ORC_ST_NONFINITE;
         else if (fabs(tip(&dv, y)) > mo->div_limit * mo->free_amplitude) status |= ORC_ST_DIVERGED;
         if (status || in_window) continue;
-        double Ac, ph;
-        orc_lockin(u, N, N, 1, &Ac, &ph);
-        if (Aprev > 0.0 && fabs(Ac - Aprev) < rtol * Ac) T = c + 1;
-        Aprev = Ac;
+        strobe(&dv, y, P);
+        if (hypot(P[0] - Pprev[0], P[1] - Pprev[1]) < rtol * hypot(P[0], P[1])) T = c + 1;
+        Pprev[0] = P[0];
+        Pprev[1] = P[1];
     }
     if (periods) *periods = c;
     if (status == 0) {
@@ -514,7 +522,6 @@ int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, d
         *J = INFINITY;
     }
     if (trace) memcpy(trace, win, sizeof(double) * W);
-    free(u);
     free(win);
     return status;
 }

@@ -111,10 +111,14 @@ template <int LAW, typename R> struct Law;
 template <typename R> struct Law<AFM_LAW_DMT, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = true;
-    R zc, a0, BH, BHa, BE, ce, cea0, clim;
+    R zc, a0, BH, BHa, BE, ce, cea0, clim, dskip;
     Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
+        // the skip form's contact test d < dskip: the Hertz term of the branch-free form can be
+        // nonzero only below ce a0 / ce (FP32-rounded), which lies within a few ulps of a0, so
+        // a0 + 2^-20 |a0| is above it; gaps between the two add exact zeros either way
+        dskip = (R)(a0n + ::fabs(a0n) * 0x1p-20);
         const double bh = -K.G * p[1] * p[4] / (6.0 * K.k) * 1e27;
         const double be = K.G * (4.0 / 3.0) * p[2] * ::sqrt(p[4]) * kSqrtNano / K.k;
         zc = (R)(p[0] * 1e9);
@@ -135,9 +139,10 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
                 // instructions per pass of the time loop
                 const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
                 R f = Ops<R>::fma(BH * r, r, b);
-                // the Hertz term is zero unless d < a0 (up to the rounding of ce a0, which
-                // gives at most a term of (1 ulp of ce a0)^{3/2} at d = a0)
-                if (FM == kFmFree || __builtin_amdgcn_ballot_w64(d < a0) != 0) {
+                // the Hertz term is zero unless d < a0 (up to the rounding of ce a0); the skip
+                // form skips it only when every lane of the wave is above dskip, where the
+                // branch-free form adds an exact zero, so both give the same bits in every lane
+                if (FM == kFmFree || __builtin_amdgcn_ballot_w64(d < dskip) != 0) {
                     // a scheduling barrier (no instruction, no memory effect) keeps the compiler
                     // from speculating this block into a select evaluated on every pass
                     if constexpr (FM == kFmSkip) __builtin_amdgcn_sched_barrier(0);

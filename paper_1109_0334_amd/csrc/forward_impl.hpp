@@ -63,16 +63,45 @@ struct DriveP {
     }
 };
 
+// Stroboscopic point of the orbit at a period's end (the same drive phase every time): the
+// deflection u and its rate u' per unit tau (nm), FP64 with the Kahan residuals.  For a steady
+// sinusoid |(u, u')| is its amplitude.
+template <int NM, bool COMP, typename R>
+__device__ __forceinline__ void strobe(const R (&x)[NM], const R (&v)[NM], const R (&cx)[NM],
+                                       const R (&cv)[NM], double zc, double &u, double &ud) {
+    u = sample<NM, COMP>(x, cx, zc);
+    ud = 0.0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        ud += (double)v[i];
+        if constexpr (COMP) ud -= (double)cv[i];
+    }
+}
+
+// Adaptive steady-state test at a period's end: the point moved by less than rtol of its size
+// since the previous period's end (Pu, Pv, updated here).
+template <int NM, bool COMP, typename R>
+__device__ __forceinline__ bool steady_exit(const R (&x)[NM], const R (&v)[NM], const R (&cx)[NM],
+                                            const R (&cv)[NM], double zc, double rtol, double &Pu,
+                                            double &Pv) {
+    double u, ud;
+    strobe<NM, COMP>(x, v, cx, cv, zc, u, ud);
+    const double du = u - Pu, dv = ud - Pv;
+    const double d2 = __builtin_fma(du, du, dv * dv), a2 = __builtin_fma(u, u, ud * ud);
+    Pu = u;
+    Pv = ud;
+    return d2 < rtol * rtol * a2;
+}
+
 // Integrate T trajectories of nc periods each in one lane and reduce them.  zc: separations in
 // nm (FP64).  Urow: measured window traces (m) or nullptr; trow: window trace outputs (m) or
 // nullptr.  With T > 1 the trajectories advance step by step side by side (independent
 // instruction streams the scheduler interleaves) and share the drive-table loads; a trajectory
 // that fails keeps being stepped (its results are discarded) until all have failed.  DP: the
 // drive comes from the trajectory's own base-motion parameters (dv) instead of the table (one
-// trajectory per lane).  EX: adaptive steady-state exit (one trajectory per lane): after every
-// transient period the lane compares that period's lock-in amplitude with the previous one's and,
-// once they differ by less than K.steady_rtol relative, starts its window with the next period
-// (nc stays the cap).
+// trajectory per lane).  EX: adaptive steady-state exit (one trajectory per lane, steady_exit):
+// once a transient period's end point moved by less than K.steady_rtol of its size, the window
+// starts with the next period (nc stays the cap).
 template <int LAW, int NM, bool MIXED, int FM, int T, bool DP, bool EX>
 __device__ __forceinline__ void integrate(
     const Law<LAW, typename std::conditional<MIXED, float, double>::type> (&law)[T],
@@ -117,46 +146,12 @@ __device__ __forceinline__ void integrate(
     }
     R Dc = R(0);  // DP: drive term at the start of the next step
     if constexpr (DP) Dc = dv.at(0.0);
-    double Aprev = -1.0;  // EX: previous transient period's lock-in amplitude
+    // EX: the stroboscopic point (u, u') of the previous period's end (first: the initial state)
+    double Pu = 0.0, Pv = 0.0;
+    if constexpr (EX) strobe<NM, COMP>(x[0], v[0], cx[0], cv[0], zc[0], Pu, Pv);
 
     for (int c = 0; c < c_win + K.lockin; ++c) {
-        if (EX && c < c_win) {
-            // transient period with the one-period lock-in of the deflection
-            double Pc = 0.0, Ps = 0.0;
-            auto tsum = [&](int s) {
-                const double u = sample<NM, COMP>(x[0], cx[0], zc[0]);
-                Pc = __builtin_fma(u, Lc[s + 1], Pc);
-                Ps = __builtin_fma(u, Ls[s + 1], Ps);
-            };
-            int s = 0;
-            for (; s + 4 <= N; s += 4) {
-                using CR = const __attribute__((address_space(4))) R;
-                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
-                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
-                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
-                                       e0, e1, e2);
-                tsum(s);
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
-                                       e2, e3, e4);
-                tsum(s + 1);
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
-                                       e4, e5, e6);
-                tsum(s + 2);
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
-                                       e6, e7, e8);
-                tsum(s + 3);
-            }
-            for (; s < N; ++s) {
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
-                                       Dt[2 * s], Dt[2 * s + 1], Dt[2 * s + 2]);
-                tsum(s);
-            }
-            const double X = 2.0 * Pc / N, Y = 2.0 * Ps / N;
-            const double A = ::sqrt(__builtin_fma(X, X, Y * Y));
-            if (Aprev > 0.0 && fabs(A - Aprev) < K.steady_rtol * A) c_win = c + 1;
-            Aprev = A;
-        } else if (DP && c < c_win) {
+        if (DP && c < c_win) {
             const double jb = 2.0 * ((double)c * N);
             for (int s = 0; s < N; ++s) {
                 const double j = jb + 2.0 * s;
@@ -283,6 +278,13 @@ __device__ __forceinline__ void integrate(
             alive = alive || !st[t];
         }
         if (!alive) break;
+        if constexpr (EX) {
+            // the transient ends after the first period whose end point moved by less than
+            // steady_rtol of its size
+            if (c < c_win && steady_exit<NM, COMP>(x[0], v[0], cx[0], cv[0], zc[0], K.steady_rtol,
+                                                   Pu, Pv))
+                c_win = c + 1;
+        }
     }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -648,6 +650,176 @@ __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KC
     }
 }
 
+// Persistent lane-refill kernel for the adaptive steady-state exit on uneven batches (the
+// work-queue batches of afm_invert).  With the exit, trajectories end at their own periods, so a
+// wave that kept its 64 trajectories would run until the slowest of them settled.  Here every
+// lane owns one trajectory at a time: at each period boundary the lanes whose trajectory has
+// finished take the next trajectories of the longest-first order (one atomic per wave, ranks by
+// ballot), so the waves stay full until the work runs out, and every wave leaves once no lane has
+// work and the order is exhausted.  All lanes of a wave step in period lock-step (same step
+// index, so the drive loads stay uniform); a lane's transient periods are plain RK4 steps with
+// the steady-state test at their ends, its window periods add the lock-in and misfit terms.
+// Per trajectory the arithmetic is that of the one-lane kernel with the exit (k_forward<..., EX>,
+// whose branch-free law form adds the same terms as the skip form used here), so the results are
+// the same bits.
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(256) k_forward_lanes(const FwdArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    constexpr bool COMP = MIXED;
+    // the wave-uniform contact skip (the lanes of a wave step in period lock-step, so their
+    // contacts cluster in the same part of the drive period); it adds the same terms as the
+    // branch-free form of the one-lane kernel
+    constexpr int FM = Law<LAW, float>::kBranch ? kFmSkip : kFmFree;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    const double *__restrict__ Lc = K.lock_c;
+    const double *__restrict__ Ls = K.lock_s;
+    const int lane = threadIdx.x & 63;
+    const int N = K.N, L = K.lockin;
+    const int64_t W = (int64_t)L * N;
+    const int64_t total = (int64_t)A.n_items * 64;
+    R om2[NM], cd[NM], gn[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        om2[m] = (R)K.om2[m];
+        cd[m] = (R)K.cdamp[m];
+        gn[m] = (R)K.gain[m];
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+
+    // this lane's trajectory
+    int64_t i = -1;      // trajectory index, -1: none
+    bool fetch = true;   // the lane needs a trajectory
+    bool exhausted = false;
+    int c = 0, c_win = 0, nc = 0;
+    double zc = 0.0, Pu = 0.0, Pv = 0.0, Pc = 0.0, Ps = 0.0, Jn = 0.0, Jd = 0.0;
+    const double *Urow = nullptr;
+    Law<LAW, R> law;
+    R x[NM], v[NM], cx[NM], cv[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) x[m] = v[m] = cx[m] = cv[m] = R(0);
+
+    auto finish = [&](double Aout, double phi, double J, int32_t st, int32_t used) {
+        if (A.amp) A.amp[i] = Aout;
+        if (A.phase) A.phase[i] = phi;
+        if (A.J) A.J[i] = J;
+        if (A.status) A.status[i] = st;
+        if (A.periods) A.periods[i] = used;
+    };
+
+    for (;;) {
+        // refill: lanes without a trajectory take the next ones in order (padding entries of a
+        // swarm's last chunk and bad inputs are passed over)
+        for (;;) {
+            const uint64_t need = __ballot(fetch && !exhausted);
+            if (need == 0) break;
+            const int first = __ffsll((unsigned long long)need) - 1;
+            const int cnt = __popcll(need);
+            int base = 0;
+            if (lane == first) base = atomicAdd(A.head, cnt);
+            base = __shfl(base, first, 64);
+            if (fetch && !exhausted) {
+                const int64_t t = (int64_t)base + __popcll(need & ((1ull << lane) - 1ull));
+                if (t < total) {
+                    const int id = A.items[t >> 6];
+                    const int64_t grp = id / A.chunks;
+                    const int64_t local = (int64_t)(id % A.chunks) * 64 + (t & 63);
+                    if (local < A.group) {
+                        i = grp * A.group + local;
+                        nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+                        const int64_t row = A.target_id ? (int64_t)A.target_id[grp]
+                                                        : (A.row_by_group ? grp : 0);
+                        if (nc < L || row < 0 || row >= A.n_targets) {
+                            finish(NAN, NAN, INFINITY, AFM_ST_BAD_INPUT, 0);
+                        } else {
+                            double p[kMaxParams];
+                            load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+                            law = Law<LAW, R>(p, K);
+                            zc = p[0] * 1e9;
+                            Urow = A.targets + row * W;
+#pragma unroll
+                            for (int m = 0; m < NM; ++m) {
+                                x[m] = (R)(m == 0 ? zc + K.y0[0] : K.y0[m]);
+                                v[m] = (R)K.y0[NM + m];
+                                cx[m] = R(0);
+                                cv[m] = R(0);
+                            }
+                            c = 0;
+                            c_win = nc - L;
+                            strobe<NM, COMP>(x, v, cx, cv, zc, Pu, Pv);
+                            Jn = Jd = 0.0;
+                            fetch = false;
+                        }
+                    }
+                }
+            }
+            if ((int64_t)base + cnt >= total) exhausted = true;  // the same for every lane
+        }
+        const bool act = !fetch;
+        if (__ballot(act) == 0) break;  // no lane has work and the order is exhausted
+
+        // one period for every lane with a trajectory
+        if (act) {
+            const bool inwin = c >= c_win;
+            if (c == c_win) Pc = Ps = 0.0;
+            const int64_t w0 = inwin ? (int64_t)(c - c_win) * N : 0;
+            // the window's lock-in and misfit terms, for the lanes in their window only
+            auto book = [&](int s) {
+                if (inwin) {
+                    const double u = sample<NM, COMP>(x, cx, zc);
+                    Pc = __builtin_fma(u, Lc[s + 1], Pc);
+                    Ps = __builtin_fma(u, Ls[s + 1], Ps);
+                    const double U = Urow[w0 + s] * 1e9;
+                    const double e = U - u;
+                    Jn = __builtin_fma(e, e, Jn);
+                    Jd = __builtin_fma(U, U, Jd);
+                }
+            };
+            int s = 0;
+            for (; s + 4 <= N; s += 4) {
+                using CR = const __attribute__((address_space(4))) R;
+                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
+                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
+                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e0, e1, e2);
+                book(s);
+                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e2, e3, e4);
+                book(s + 1);
+                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e4, e5, e6);
+                book(s + 2);
+                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, e6, e7, e8);
+                book(s + 3);
+            }
+            for (; s < N; ++s) {
+                rk4_step<NM, COMP, FM>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                            Dt[2 * s + 1], Dt[2 * s + 2]);
+                book(s);
+            }
+            // end of the period: health, the exit test, or the window's end
+            bool fin = true;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) fin = fin && isfinite(x[m]) && isfinite(v[m]);
+            int32_t st = 0;
+            if (!fin) st = AFM_ST_NONFINITE;
+            else if (fabs(sample<NM, COMP>(x, cx, zc)) > K.div_nm) st = AFM_ST_DIVERGED;
+            if (st) {
+                finish(NAN, NAN, INFINITY, st, c + 1);
+                fetch = true;
+            } else if (!inwin) {
+                if (steady_exit<NM, COMP>(x, v, cx, cv, zc, K.steady_rtol, Pu, Pv)) c_win = c + 1;
+            } else if (c == c_win + L - 1) {
+                const double X = 2.0 * Pc / (double)W, Y = 2.0 * Ps / (double)W;
+                const double J = Jn / Jd;
+                finish(::sqrt(__builtin_fma(X, X, Y * Y)) * 1e-9, ::atan2(-X, Y),
+                       isfinite(J) ? J : INFINITY, 0, c + 1);
+                fetch = true;
+            }
+            ++c;
+        }
+    }
+}
+
 __global__ void k_queue_reset(int32_t *head) {
     if (threadIdx.x == 0) *head = 0;
 }
@@ -711,13 +883,15 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
     constexpr bool branchy = Law<LAW, float>::kBranch;
     if (K.steady_rtol > 0.0) {
         // adaptive steady-state exit: one trajectory per lane (each lane leaves its transient
-        // when its own amplitude settles), not tuned; the work queue keeps its longest-first
-        // order and its wave-uniform contact skip
-        if (a.items) {
+        // when its own amplitude settles), not tuned; work-queue batches refill lanes as their
+        // trajectories finish
+        // (the lane kernel keeps no window traces; its order counter stays far from overflow)
+        if (a.items && a.targets && !a.trace && !a.mtrace &&
+            (int64_t)a.n_items * 64 < ((int64_t)1 << 30)) {
             hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
             const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
-            hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree, true>),
-                               dim3(blocks), dim3(256), 0, s, a, K);
+            hipLaunchKernelGGL((k_forward_lanes<LAW, NM, MIXED>), dim3(blocks), dim3(256), 0, s,
+                               a, K);
             return hipGetLastError();
         }
         const int block = a.n < kSmallBatch ? 64 : 256;
