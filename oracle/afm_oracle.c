@@ -754,8 +754,22 @@ static double dtheta_dz(double z, double lo, double hi, int32_t log_scale) {
 /* ------------------------------------------------------------------------------------------ */
 
 /* ybar += (df/dy)^T kbar and pbar += (df/dp)^T kbar for the model right-hand side at state Y. */
-static void rhs_vjp(const orc_model *mo, const orc_derived *dv, const double *p, const double *Y,
-                    const double *kbar, double *ybar, double *pbar) {
+/* Derivatives of the parameter-driven base term -y_b''(t) = a (w^2 sin(phi) - 4 pi g cos(phi)),
+ * phi = 2 pi (f + g t) t, w = 2 pi (f + 2 g t), with respect to a, f and g (Eq. 10). */
+static void base_acc_grad(const double *p, double t, double *da) {
+    double a = p[ORC_P_A], f = p[ORC_P_F], g = p[ORC_P_G];
+    double phi = 2.0 * M_PI * (f + g * t) * t, w = 2.0 * M_PI * (f + 2.0 * g * t);
+    double sn = sin(phi), cs = cos(phi);
+    da[0] = w * w * sn - 4.0 * M_PI * g * cs;
+    /* dphi/df = 2 pi t, dw/df = 2 pi; dphi/dg = 2 pi t^2, dw/dg = 4 pi t */
+    da[1] = a * (2.0 * w * 2.0 * M_PI * sn + w * w * cs * 2.0 * M_PI * t +
+                 4.0 * M_PI * g * sn * 2.0 * M_PI * t);
+    da[2] = a * (2.0 * w * 4.0 * M_PI * t * sn + w * w * cs * 2.0 * M_PI * t * t -
+                 4.0 * M_PI * cs + 4.0 * M_PI * g * sn * 2.0 * M_PI * t * t);
+}
+
+static void rhs_vjp(const orc_model *mo, const orc_derived *dv, const double *p, double t,
+                    const double *Y, const double *kbar, double *ybar, double *pbar) {
     int m = dv->m;
     double u = 0.0, ud = 0.0, sp = 0.0;
     for (int i = 0; i < m; i++) {
@@ -772,6 +786,14 @@ static void rhs_vjp(const orc_model *mo, const orc_derived *dv, const double *p,
     int np = orc_law_param_count(mo->law);
     pbar[0] += Fd / dv->M * sp; /* z_c enters through d = z_c + u */
     for (int j = 1; j < np; j++) pbar[j] += Fp[j] / dv->M * sp;
+    if (mo->drive_mode == ORC_DRIVE_PARAMS) { /* gamma_i (-y_b'') enters every velocity slope */
+        double sg = 0.0, da[3];
+        for (int i = 0; i < m; i++) sg += mo->gain[i] * kbar[m + i];
+        base_acc_grad(p, t, da);
+        pbar[ORC_P_A] += sg * da[0];
+        pbar[ORC_P_F] += sg * da[1];
+        pbar[ORC_P_G] += sg * da[2];
+    }
 }
 
 /* Misfit J and its exact gradient with respect to every entry of p (SI), by reverse-mode
@@ -785,12 +807,7 @@ int orc_misfit_grad(const orc_model *mo, const double *p, int32_t n_cycles, cons
                     double *J_out, double *grad) {
     orc_derived dv;
     derive(mo, &dv);
-    int m = dv.m, ns = 2 * m, np = orc_law_param_count(mo->law);
-    if (mo->drive_mode != ORC_DRIVE_TABLE) { /* the base motion's derivatives are not built */
-        for (int j = 0; j < ORC_MAX_PARAMS; j++) grad[j] = NAN;
-        *J_out = NAN;
-        return 8;
-    }
+    int m = dv.m, ns = 2 * m, np = param_count(mo);
     int64_t N = mo->steps_per_cycle, Ntot = (int64_t)n_cycles * N, W = (int64_t)mo->lockin_cycles * N;
     double *ys = (double *)malloc(sizeof(double) * ns * (Ntot + 1));
     orc_initial_state(mo, ys);
@@ -846,13 +863,14 @@ int orc_misfit_grad(const orc_model *mo, const double *p, int32_t n_cycles, cons
         for (int i = 0; i < ns; i++) Ys[3][i] = y[i] + h * ks[2][i];
         double Ybar[4][2 * ORC_MAX_MODES], kbar[2 * ORC_MAX_MODES];
         const double a_next[4] = {0.5, 0.5, 1.0, 0.0}; /* a_{i+1,i} */
+        const double c_st[4] = {0.0, 0.5, 0.5, 1.0};   /* stage times, in steps */
         for (int st = 3; st >= 0; st--) {
             for (int i = 0; i < ns; i++) {
                 kbar[i] = h * b[st] * ybar[i];
                 if (st < 3) kbar[i] += h * a_next[st] * Ybar[st + 1][i];
             }
             for (int i = 0; i < ns; i++) Ybar[st][i] = 0.0;
-            rhs_vjp(mo, &dv, p, Ys[st], kbar, Ybar[st], pbar);
+            rhs_vjp(mo, &dv, p, t + c_st[st] * h, Ys[st], kbar, Ybar[st], pbar);
         }
         for (int i = 0; i < ns; i++) ybar[i] += Ybar[0][i] + Ybar[1][i] + Ybar[2][i] + Ybar[3][i];
     }

@@ -23,7 +23,7 @@ def _force(law, p, d, dd):
                 F += -p[5] * cmath.sqrt(R * dl) * dd
         return F
     if law == "lj":
-        zc, eps, r0, n, m = p
+        zc, eps, r0, n, m = p[:5]
         s = r0 / d
         ls = cmath.log(s)
         return eps * (n * m / (n - m)) / d * (cmath.exp(n * ls) - cmath.exp(m * ls))
@@ -50,11 +50,19 @@ def misfit(model, p, U, y0, a, n_cycles=None):
     h = 1.0 / (model["drive_freq"] * N)
     p = [complex(x) for x in p]
 
+    params_drive = model.get("drive", "table") == "params"
+
     def rhs(t, y):
         u = sum(y[:nm])
         ud = sum(y[nm:])
         F = _force(law, p, p[0] + u, ud)
-        drive = a * wd * wd * math.sin(wd * t)
+        if params_drive:  # Eq. 10 with (a, f, g) = p[8], p[9], p[10]: -y_b''
+            ab, fb, gb = p[8], p[9], p[10]
+            phi = 2 * math.pi * (fb + gb * t) * t
+            wb = 2 * math.pi * (fb + 2 * gb * t)
+            drive = ab * (wb * wb * cmath.sin(phi) - 4 * math.pi * gb * cmath.cos(phi))
+        else:
+            drive = a * wd * wd * math.sin(wd * t)
         return [y[nm + i] for i in range(nm)] + [
             -w[i] * w[i] * y[i] - c[i] * y[nm + i] + F / M + g[i] * drive for i in range(nm)]
 

@@ -9,7 +9,9 @@ p[9], p[10]).
   tip force off), fitted by least squares at f from the trajectory;
 * a chirp's response matches an independent adaptive integrator (scipy's DOP853) of the same
   motion written in absolute coordinates, where only y_b and its rate enter: this fixes the
-  sign and form of the base acceleration the oracle derives for the chirp."""
+  sign and form of the base acceleration the oracle derives for the chirp;
+* the reverse-mode gradient with respect to a, f, g equals the complex-step derivative of an
+  independent restatement of the discrete map."""
 import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
@@ -92,8 +94,30 @@ def test_chirp_against_adaptive_integrator(orc):
     assert abs(yend[1] - ref[1]) < 1e-7 * a * q * w0
 
 
-def test_misfit_gradient_reports_unsupported(orc):
-    m = _model(n_cycles=4, lockin=2)
-    U = np.ones(512) * 1e-9
-    st, J, g = orc.misfit_grad(m, _p(0.05e-9, 300e3), U)
-    assert st == 8 and np.all(np.isnan(g))
+@pytest.mark.parametrize("case", ["none1", "dmt1", "kv3"])
+def test_misfit_gradient_matches_complex_step(orc, case):
+    """The oracle's reverse-mode gradient with respect to the base motion's a, f, g (and the law's
+    constants) equals the complex-step derivative of an independent restatement of the same
+    discrete map (tests/cs_model.py)."""
+    import cs_model
+
+    if case == "kv3":
+        m = dict(_model(N=64, n_cycles=6, lockin=2), law="kv", n_modes=3, q=[400.0] * 3,
+                 ratio=[1.0, 6.27, 17.55], gain=[1.565984, -0.867872, 0.508851])
+        p = _p(0.3e-9, 297e3, 2e9)
+        p[:6] = [3e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9, 10.0]
+    else:
+        m = dict(_model(N=64, n_cycles=6, lockin=2), law=case[:-1])
+        p = _p(0.3e-9, 297e3, 2e9)
+        p[:5] = [3e-9, 6.4e-20, 1e9, 0.3e-9, 10e-9] if case == "dmt1" else [3e-9, 0, 0, 0, 0]
+    tr = orc.forward(m, p, want_trace=True)["trace"]
+    U = 0.9 * tr + 1e-10
+    st, J, g = orc.misfit_grad(m, p, U)
+    assert st == 0
+    Jc, gc = cs_model.gradient(m, list(p), list(U), [0.0] * (2 * m["n_modes"]), 0.0)
+    assert abs(J / Jc - 1) < 1e-12
+    for j in (8, 9, 10):
+        assert abs(g[j] - gc[j]) <= 1e-8 * abs(gc[j]), (j, g[j], gc[j])
+    law_slots = {"none1": [0], "dmt1": [0, 1, 2, 3], "kv3": [0, 1, 2, 3, 5]}[case]
+    for j in law_slots:
+        assert abs(g[j] - gc[j]) <= 1e-8 * max(abs(gc[j]), 1e-30), (j, g[j], gc[j])
