@@ -90,8 +90,9 @@ enum { AFM_LAW_DMT = 0, AFM_LAW_LJ = 1, AFM_LAW_KV = 2, AFM_LAW_HOOKE = 3, AFM_L
  * stays 1 / (drive_freq N) and the lock-in projects onto drive_freq.  PARAMS requires
  * ic = AFM_IC_REST (the free steady state of a chirp is not defined).  Launch shapes as for
  * TABLE (afm_set_launch_shape) without two trajectories per lane; with one lane per mode the
- * lanes of a trajectory split its drive evaluations between them.  Not built for PARAMS: the
- * adjoint (afm_grad_batch, afm_polish and the invert polish return AFM_ERR_UNSUPPORTED). */
+ * lanes of a trajectory split its drive evaluations between them.  The adjoint
+ * (afm_grad_batch, afm_polish, the invert polish) differentiates a, f, g too, one lane per
+ * trajectory. */
 enum { AFM_DRIVE_TABLE = 0, AFM_DRIVE_PARAMS = 1 };
 enum { AFM_P_BASE_A = 8, AFM_P_BASE_F = 9, AFM_P_BASE_G = 10 };
 

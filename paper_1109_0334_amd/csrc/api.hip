@@ -346,8 +346,6 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
         return fail(AFM_ERR_INVALID, "targets, J, dJ and status are required");
     if (n > 0 && n_targets < 1) return fail(AFM_ERR_INVALID, "n_targets < 1");
     if (ckpt_stride < 0) return fail(AFM_ERR_INVALID, "ckpt_stride < 0");
-    if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
-        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
     if (plan->kc.steady_rtol > 0.0)
         return fail(AFM_ERR_UNSUPPORTED, "the adjoint of the adaptive steady-state exit is not built");
     if (n == 0) return AFM_OK;
@@ -411,8 +409,6 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     if (n < 0 || steps < 0) return fail(AFM_ERR_INVALID, "n and steps must be >= 0");
     if (plan->prob.n_free < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
-    if (plan->kc.drive_mode != AFM_DRIVE_TABLE)
-        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
     if (plan->kc.steady_rtol > 0.0)
         return fail(AFM_ERR_UNSUPPORTED, "the adjoint of the adaptive steady-state exit is not built");
     if (n == 0) return AFM_OK;

@@ -30,38 +30,6 @@ struct LaneOut {
     int32_t used;  // periods integrated (transient + window, or up to a failure)
 };
 
-// Base motion from a trajectory's own parameters: the chirp of Eq. 10 (g = 0 gives Eq. 9), with
-// a, f, g in parameter slots 8, 9, 10.  at(j) is the drive term -y_b'' / wd^2 in nm at half-step
-// j (time j h / 2, i.e. s = j / (2 N) drive periods): phase in revolutions rho = s (r0 + gam s),
-// rate w = r0 + 2 gam s in units of wd, term amp (w^2 sin(2 pi rho) - (gam / pi) cos(2 pi rho)),
-// r0 = f / f_d, gam = g / f_d^2.  The phase is formed and reduced to [-1/2, 1/2] in FP64 (it
-// reaches thousands of revolutions), the sine and cosine are taken in R.
-template <typename R>
-struct DriveP {
-    double c1 = 0, c2 = 0, c3 = 0, r0 = 0;  // rho = j (c1 + j c2), w = r0 + j c3
-    R amp = R(0), kg = R(0);
-    DriveP() = default;
-    __device__ DriveP(const double (&p)[kMaxParams], const KConst &K, int nm) {
-        const double inv2n = 1.0 / (2.0 * K.N);
-        const double gam = p[AFM_P_BASE_G] / (K.fref * K.fref);
-        r0 = p[AFM_P_BASE_F] / K.fref;
-        c1 = r0 * inv2n;
-        c2 = gam * inv2n * inv2n;
-        c3 = 2.0 * gam * inv2n;
-        // a point mass carries its gain in the drive term (as the fixed drive table does)
-        amp = (R)(p[AFM_P_BASE_A] * 1e9 * (nm == 1 ? K.gain[0] : 1.0));
-        kg = (R)(gam / M_PI);
-    }
-    __device__ __forceinline__ R at(double j) const {
-        const double rho = j * __builtin_fma(j, c2, c1);
-        const double r = rho - __builtin_rint(rho);
-        const R w = (R)__builtin_fma(j, c3, r0);
-        R sn, cs;
-        if constexpr (std::is_same<R, float>::value) sincospif(2.0f * (float)r, &sn, &cs);
-        else sincospi(2.0 * r, &sn, &cs);
-        return amp * Ops<R>::fma(w * w, sn, -(kg * cs));
-    }
-};
 
 // Stroboscopic point of the orbit at a period's end (the same drive phase every time): the
 // deflection u and its rate u' per unit tau (nm), FP64 with the Kahan residuals.  For a steady

@@ -58,13 +58,28 @@ __device__ __forceinline__ void stage_eval(const L &law, const R (&x)[NM], const
     }
 }
 
-// Reverse one RK4 step y_n -> y_{n+1}: on entry (xb, vb) = dJ/dy_{n+1}, on exit dJ/dy_n.
-template <int NM, class L, typename R>
+// Adjoint of a stage's drive term D from the adjoint of its velocity slopes: D enters slope i
+// with the mode's gain (a point mass carries its gain in D itself).
+template <int NM, typename R>
+__device__ __forceinline__ R drive_adjoint(const R (&kbv)[NM], const R (&gn)[NM]) {
+    if constexpr (NM == 1) {
+        return kbv[0];
+    } else {
+        R d = R(0);
+#pragma unroll
+        for (int i = 0; i < NM; ++i) d = Ops<R>::fma(gn[i], kbv[i], d);
+        return d;
+    }
+}
+
+// Reverse one RK4 step y_n -> y_{n+1}: on entry (xb, vb) = dJ/dy_{n+1}, on exit dJ/dy_n.  DP:
+// also accumulates the adjoints of the step's drive terms D0, D1 (two stages), D2 into Db.
+template <int NM, class L, bool DP = false, typename R>
 __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], const R (&v)[NM],
                                              R (&xb)[NM], R (&vb)[NM], const R (&om2)[NM],
                                              const R (&cd)[NM], const R (&gn)[NM], R h, R h2,
                                              R h3, R h6, R D0, R D1, R D2, R (&gsf)[L::NC],
-                                             R &gzf) {
+                                             R &gzf, R (&Db)[3]) {
     // recompute the four stage states and the force partials there
     R a1[NM], a2[NM], a3[NM], a4[NM], Y[NM], V2[NM], V3[NM], V4[NM];
     R Fd1, Fdd1, Fd2, Fdd2, Fd3, Fdd3, Fd4, Fdd4;
@@ -95,6 +110,7 @@ __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], con
         kbx[i] = h6 * xb[i];
         kbv[i] = h6 * vb[i];
     }
+    if constexpr (DP) Db[2] += drive_adjoint<NM>(kbv, gn);
     stage_vjp<NM, L>(kbx, kbv, Fd4, Fdd4, dc4, om2, cd, Ybx, Ybv, gsf, gzf);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
@@ -103,6 +119,7 @@ __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], con
         kbx[i] = Ops<R>::fma(h3, xb[i], h * Ybx[i]);
         kbv[i] = Ops<R>::fma(h3, vb[i], h * Ybv[i]);
     }
+    if constexpr (DP) Db[1] += drive_adjoint<NM>(kbv, gn);
     stage_vjp<NM, L>(kbx, kbv, Fd3, Fdd3, dc3, om2, cd, Ybx, Ybv, gsf, gzf);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
@@ -111,6 +128,7 @@ __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], con
         kbx[i] = Ops<R>::fma(h3, xb[i], h2 * Ybx[i]);
         kbv[i] = Ops<R>::fma(h3, vb[i], h2 * Ybv[i]);
     }
+    if constexpr (DP) Db[1] += drive_adjoint<NM>(kbv, gn);
     stage_vjp<NM, L>(kbx, kbv, Fd2, Fdd2, dc2, om2, cd, Ybx, Ybv, gsf, gzf);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
@@ -119,6 +137,7 @@ __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], con
         kbx[i] = Ops<R>::fma(h6, xb[i], h2 * Ybx[i]);
         kbv[i] = Ops<R>::fma(h6, vb[i], h2 * Ybv[i]);
     }
+    if constexpr (DP) Db[0] += drive_adjoint<NM>(kbv, gn);
     stage_vjp<NM, L>(kbx, kbv, Fd1, Fdd1, dc1, om2, cd, Ybx, Ybv, gsf, gzf);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
@@ -127,7 +146,9 @@ __device__ __forceinline__ void reverse_step(const L &law, const R (&x)[NM], con
     }
 }
 
-template <int LAW, int NM, bool MIXED>
+// DP: the parameter-driven base motion (drive terms evaluated per lane, as the forward kernel
+// does, and the derivatives of the drive with respect to a, f, g accumulated in FP64).
+template <int LAW, int NM, bool MIXED, bool DP = false>
 __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     using R = typename std::conditional<MIXED, float, double>::type;
     using L = Law<LAW, R>;
@@ -160,6 +181,25 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     const R *__restrict__ Dt;
     if constexpr (MIXED) Dt = K.drive_f;
     else Dt = K.drive_d;
+    DriveP<R> dv;
+    DriveGrad dgr;
+    if constexpr (DP) {
+        dv = DriveP<R>(p, K, NM);
+        dgr = DriveGrad(p, K, NM);
+    }
+    // drive terms of global step n at t_n, t_n + h/2, t_n + h: the table's or this lane's own
+    auto drive3 = [&](int64_t n, int s, R &d0, R &d1, R &d2) {
+        if constexpr (DP) {
+            const double j = 2.0 * (double)n;
+            d0 = dv.at(j);
+            d1 = dv.at(j + 1.0);
+            d2 = dv.at(j + 2.0);
+        } else {
+            d0 = Dt[2 * s];
+            d1 = Dt[2 * s + 1];
+            d2 = Dt[2 * s + 2];
+        }
+    };
 
     R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
 #pragma unroll
@@ -210,8 +250,9 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 cdn = kc;
             }
             --cdn;
-            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                     Dt[2 * s + 1], Dt[2 * s + 2]);
+            R d0, d1, d2;
+            drive3(n, s, d0, d1, d2);
+            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (n + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
                 const double U = Urow[n + 1 - first_w] * 1e9;
@@ -244,6 +285,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
 #pragma unroll
     for (int k = 0; k < L::NC; ++k) gs[k] = 0.0;
     double gz = 0.0;
+    double gD[3] = {0.0, 0.0, 0.0};  // DP: dJ/d(a, f, g)
     const int64_t nseg = (Ntot + kc - 1) / kc;
     for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
         const int64_t n0 = sgi * kc;
@@ -276,8 +318,9 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                     sgd[(k * NB + NM + m) * n_lanes + i] = v[m];
                 }
             }
-            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                     Dt[2 * s + 1], Dt[2 * s + 2]);
+            R d0, d1, d2;
+            drive3(q, s, d0, d1, d2);
+            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (q + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
                 const double ub = coef * (Urow[q + 1 - first_w] * 1e9 - u);
@@ -314,11 +357,24 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
 #pragma unroll
             for (int k = 0; k < L::NC; ++k) gsf[k] = R(0);
             R gzf = R(0);
-            reverse_step<NM, L>(law, yx, yv, xb, vb, om2, cd, gn, h, h2, h3, h6, Dt[2 * s],
-                                Dt[2 * s + 1], Dt[2 * s + 2], gsf, gzf);
+            R Db[3] = {R(0), R(0), R(0)};
+            R d0, d1, d2;
+            drive3(q, s, d0, d1, d2);
+            reverse_step<NM, L, DP>(law, yx, yv, xb, vb, om2, cd, gn, h, h2, h3, h6, d0, d1, d2,
+                                    gsf, gzf, Db);
 #pragma unroll
             for (int k = 0; k < L::NC; ++k) gs[k] += (double)gsf[k];
             gz += (double)gzf;
+            if constexpr (DP) {
+                double e0[3], e1[3], e2[3];
+                const double j = 2.0 * (double)q;
+                dgr.at(j, e0);
+                dgr.at(j + 1.0, e1);
+                dgr.at(j + 2.0, e2);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    gD[k] += (double)Db[0] * e0[k] + (double)Db[1] * e1[k] + (double)Db[2] * e2[k];
+            }
             s = s == 0 ? N - 1 : s - 1;
         }
     }
@@ -327,6 +383,11 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
 #pragma unroll
     for (int q = 0; q < kMaxParams; ++q) g[q] = 0.0;
     L::to_si(p, K, gs, gz, g);
+    if constexpr (DP) {
+        g[AFM_P_BASE_A] = gD[0];
+        g[AFM_P_BASE_F] = gD[1];
+        g[AFM_P_BASE_G] = gD[2];
+    }
     A.J[i] = J;
     for (int j = 0; j < K.n_free; ++j) {
         double gj = 0.0;
@@ -614,6 +675,12 @@ __global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
     const int block = 64;
+    if (K.drive_mode != AFM_DRIVE_TABLE) {  // parameter-driven base: one lane per trajectory
+        const int64_t grid = (a.n + block - 1) / block;
+        hipLaunchKernelGGL((k_grad<LAW, NM, MIXED, true>), dim3((unsigned)grid), dim3(block), 0, s,
+                           a, K);
+        return hipGetLastError();
+    }
     if constexpr (NM > 1) {
         if (a.mp) {
             constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);

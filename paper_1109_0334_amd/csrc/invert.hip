@@ -115,8 +115,6 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
         return fail(AFM_ERR_INVALID, "targets and outputs are required");
     if (lbfgs_steps < 0 || lbfgs_topk < 0 || lbfgs_topk > particles)
         return fail(AFM_ERR_INVALID, "need 0 <= lbfgs_steps and 0 <= lbfgs_topk <= particles");
-    if (lbfgs_steps > 0 && lbfgs_topk > 0 && plan->kc.drive_mode != AFM_DRIVE_TABLE)
-        return fail(AFM_ERR_UNSUPPORTED, "the adjoint of a parameter-driven base motion is not built");
     if (lbfgs_steps > 0 && lbfgs_topk > 0 && plan->kc.steady_rtol > 0.0)
         return fail(AFM_ERR_UNSUPPORTED, "the adjoint of the adaptive steady-state exit is not built");
     const int32_t kpol = lbfgs_steps > 0 ? lbfgs_topk : 0;

@@ -113,6 +113,71 @@ __device__ __forceinline__ void rk4_step(const L &law, R (&x)[NM], R (&v)[NM], R
     }
 }
 
+// Base motion from a trajectory's own parameters: the chirp of Eq. 10 (g = 0 gives Eq. 9), with
+// a, f, g in parameter slots 8, 9, 10.  at(j) is the drive term -y_b'' / wd^2 in nm at half-step
+// j (time j h / 2, i.e. s = j / (2 N) drive periods): phase in revolutions rho = s (r0 + gam s),
+// rate w = r0 + 2 gam s in units of wd, term amp (w^2 sin(2 pi rho) - (gam / pi) cos(2 pi rho)),
+// r0 = f / f_d, gam = g / f_d^2.  The phase is formed and reduced to [-1/2, 1/2] in FP64 (it
+// reaches thousands of revolutions), the sine and cosine are taken in R.
+template <typename R>
+struct DriveP {
+    double c1 = 0, c2 = 0, c3 = 0, r0 = 0;  // rho = j (c1 + j c2), w = r0 + j c3
+    R amp = R(0), kg = R(0);
+    DriveP() = default;
+    __device__ DriveP(const double (&p)[kMaxParams], const KConst &K, int nm) {
+        const double inv2n = 1.0 / (2.0 * K.N);
+        const double gam = p[AFM_P_BASE_G] / (K.fref * K.fref);
+        r0 = p[AFM_P_BASE_F] / K.fref;
+        c1 = r0 * inv2n;
+        c2 = gam * inv2n * inv2n;
+        c3 = 2.0 * gam * inv2n;
+        // a point mass carries its gain in the drive term (as the fixed drive table does)
+        amp = (R)(p[AFM_P_BASE_A] * 1e9 * (nm == 1 ? K.gain[0] : 1.0));
+        kg = (R)(gam / M_PI);
+    }
+    __device__ __forceinline__ R at(double j) const {
+        const double rho = j * __builtin_fma(j, c2, c1);
+        const double r = rho - __builtin_rint(rho);
+        const R w = (R)__builtin_fma(j, c3, r0);
+        R sn, cs;
+        if constexpr (std::is_same<R, float>::value) sincospif(2.0f * (float)r, &sn, &cs);
+        else sincospi(2.0 * r, &sn, &cs);
+        return amp * Ops<R>::fma(w * w, sn, -(kg * cs));
+    }
+};
+
+// Derivatives of the drive term DriveP::at(j) with respect to the base motion's a (m), f (Hz)
+// and g (Hz/s), in FP64, for the adjoint: with s = j / (2 N) periods, rho = s (r0 + gam s),
+// w = r0 + 2 gam s, D = amp (w^2 sin(2 pi rho) - kg cos(2 pi rho)), amp = a 1e9 G,
+// r0 = f / f_d, gam = g / f_d^2, kg = gam / pi:
+//   dD/da = 1e9 G (w^2 sin - kg cos),
+//   dD/df = amp (2 w sin / f_d + 2 pi (w^2 cos + kg sin) s / f_d),
+//   dD/dg = amp (4 w s sin / f_d^2 + 2 pi (w^2 cos + kg sin) s^2 / f_d^2 - cos / (pi f_d^2)).
+struct DriveGrad {
+    double inv2n = 0, fref = 0, r0 = 0, gam = 0, kg = 0, scale = 0, amp = 0;
+    DriveGrad() = default;
+    __device__ DriveGrad(const double (&p)[kMaxParams], const KConst &K, int nm) {
+        inv2n = 1.0 / (2.0 * K.N);
+        fref = K.fref;
+        r0 = p[AFM_P_BASE_F] / fref;
+        gam = p[AFM_P_BASE_G] / (fref * fref);
+        kg = gam / M_PI;
+        scale = 1e9 * (nm == 1 ? K.gain[0] : 1.0);
+        amp = p[AFM_P_BASE_A] * scale;
+    }
+    __device__ void at(double j, double (&dD)[3]) const {
+        const double s = j * inv2n;
+        const double rho = s * __builtin_fma(gam, s, r0);
+        double sn, cs;
+        sincospi(2.0 * (rho - __builtin_rint(rho)), &sn, &cs);
+        const double w = __builtin_fma(2.0 * gam, s, r0);
+        const double core = __builtin_fma(w * w, cs, kg * sn);  // w^2 cos + kg sin
+        dD[0] = scale * __builtin_fma(w * w, sn, -(kg * cs));
+        dD[1] = amp * (2.0 * w * sn + 2.0 * M_PI * core * s) / fref;
+        dD[2] = amp * (4.0 * w * s * sn + 2.0 * M_PI * core * s * s - cs / M_PI) / (fref * fref);
+    }
+};
+
 // Tip deflection u = g - z_c + x_2 + ... in FP64, including the Kahan residuals (the compensated
 // state is x - c).
 template <int NM, bool COMP, typename R>

@@ -10,7 +10,8 @@ against the oracle.
   forward the swarm follows the oracle swarm step for step (1-D amplitude, 3-D chirp, the
   spring sample of Sec. 4.2, and per-swarm period counts); the mixed forward recovers the 2-D
   truth; the spring-damper sample of Sec. 4.3 forward in both precisions;
-* the adjoint of these parameters is not built: gradients and polish report unsupported."""
+* the adjoint with respect to a, f, g matches the oracle's; the polish works inside a
+  base-motion inversion."""
 import numpy as np
 import pytest
 
@@ -277,22 +278,61 @@ def test_invert_two_parameter_mixed_recovers_truth(afm, orc):
     assert abs(bt[0] / 2e-9 - 1) < 1e-3 and abs(bt[1] / 25600.0 - 1) < 1e-4
 
 
-def test_adjoint_reports_unsupported(afm):
-    import torch
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("case", ["pm_none", "kv3"])
+def test_gradient_of_base_motion_matches_oracle(afm, orc, prec, case):
+    """afm_grad_batch with the base motion's a, f, g free (and, for the 3-mode Kelvin-Voigt case,
+    z_c): the discrete adjoint against the oracle's exact one, norm-wise in the search box's
+    normalised coordinates (tolerances as for the force-law gradients)."""
+    if case == "pm_none":
+        m = _pm_model(law="none", N=128, n_cycles=20, lockin=5)
+        base = _full([0.0], 0.0, 0.0, 0.0)
+        free = _FREE_AFG
+    else:
+        c5 = W.config("c5")["model"]
+        m = dict(_pm_model(law="kv", N=128, n_cycles=20, lockin=5), n_modes=3, q=[400.0] * 3,
+                 ratio=list(c5["ratio"]), gain=list(c5["gain"]))
+        base = _full(_DMT + [10.0], 0.0, 0.0, 0.0)
+        free = [(0, 4e-9, 9e-9, 0)] + _FREE_AFG
+    th = _draw_afg(6, 41, free) if case == "pm_none" else np.vstack(
+        [np.random.default_rng(42).uniform(4e-9, 9e-9, 6), _draw_afg(6, 41)])
+    P = PT.full_from_free(base, free, th)
+    U = orc.forward(m, P[0], want_trace=True)["trace"] * 0.95
+    plan = afm.Plan(m, base, free, precision=prec)
+    J, dJ, st = (x.cpu().numpy() for x in plan.grad_batch(th, U[None, :]))
+    zs = np.array([f[2] - f[1] for f in free])[:, None]
+    for i in range(th.shape[1]):
+        so, Jo, go = orc.misfit_grad(m, P[i], U)
+        assert st[i] == 0 and so == 0
+        gfree = np.array([go[f[0]] for f in free])
+        e = np.linalg.norm((dJ[:, i] - gfree) * zs[:, 0]) / np.linalg.norm(gfree * zs[:, 0])
+        if prec == "fp64":
+            assert abs(J[i] / Jo - 1) < 1e-9
+            tol = PT.GRAD_TOL64 if e <= PT.GRAD_TOL64 else \
+                PT.grad_tolerance(orc, m, P[i], U, free, fp64=True)
+        else:
+            assert abs(J[i] - Jo) <= PT.misfit_tol(Jo)
+            tol = PT.GRAD_TOL if e <= PT.GRAD_TOL else PT.grad_tolerance(orc, m, P[i], U, free)
+        print(f"{case} {prec} point {i}: rel err {e:.2e} (tolerance {tol:.1e})")
+        assert e <= tol
 
-    m = _pm_model(n_cycles=4, lockin=2)
-    plan = afm.Plan(m, _full([8e-9], 0.05e-9, 300e3, 0.0), _FREE_AFG[:2], precision="mixed")
-    th = torch.tensor([[0.05e-9], [300e3]], dtype=torch.float64, device="cuda")
-    U = torch.zeros(1, plan.W, dtype=torch.float64, device="cuda") + 1e-9
-    with pytest.raises(afm.AfmError, match="status 4"):
-        plan.grad_batch(th, U)
-    with pytest.raises(afm.AfmError, match="status 4"):
-        plan.polish(torch.full((2, 1), 0.5, dtype=torch.float64, device="cuda"), U, steps=2)
-    with pytest.raises(afm.AfmError, match="status 4"):
-        plan.invert(U, 8, 2, seed=1, lbfgs_steps=2, lbfgs_topk=2)
-    out = plan.invert(U, 8, 2, seed=1)  # without the polish the inversion runs
-    assert out["best_J"].shape == (1,)
 
+def test_polish_of_base_motion_inversion(afm, orc):
+    """The paper's 2-D base-motion problem with the L-BFGS polish inside the inversion: the
+    polished best point is at least as good as the swarm's and near the truth."""
+    c = W.base_motion("2d")
+    m, truth, free = c["model"], c["params"], c["free"]
+    U = orc.forward(m, truth, want_trace=True)["trace"]
+    plan = afm.Plan(m, truth, free, precision="mixed")
+    plain = plan.invert(U[None, :], 64, 6, seed=4, cutoff=0.0)
+    pol = plan.invert(U[None, :], 64, 6, seed=4, cutoff=0.0, lbfgs_steps=8, lbfgs_topk=4)
+    Jp, Jl = plain["best_J"].item(), pol["best_J"].item()
+    bt = pol["best_theta"].cpu().numpy()[:, 0]
+    print(f"swarm J {Jp:.3e}, polished J {Jl:.3e}, a {bt[0]:.6e}, f {bt[1]:.3f}")
+    assert Jl <= Jp
+    p = truth.copy()
+    p[8], p[9] = bt
+    assert abs(pol["best_J"].item() - orc.forward(m, p, U)["J"]) <= PT.misfit_tol(Jl)
 
 def test_mode_count_convergence_matches_oracle(afm, orc):
     """The paper's mode-count study (Sec. 3.3): the FP64 GPU traces of the beam truncated to
