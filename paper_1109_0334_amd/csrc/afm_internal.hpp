@@ -468,6 +468,7 @@ struct FwdArgs {
     double *mtrace;            // optional window modal coordinates, m: [NM][W][mtrace_ld]
     int64_t mtrace_ld;         // (trajectory fastest)
     int32_t *periods;          // optional periods integrated per trajectory
+    int32_t xcd_stride;        // plain k_forward grid: > 1 = only every xcd_stride-th workgroup works
 };
 
 // Adjoint launch description (see afm_grad_batch).

@@ -344,7 +344,12 @@ __device__ __forceinline__ void lane_forward(const FwdArgs &A, const KConst &K,
 // parameter-driven base motion (T = 1).
 template <int LAW, int NM, bool MIXED, int FM, int T, bool DP = false, bool EX = false>
 __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K) {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * T + threadIdx.x;
+    unsigned b = blockIdx.x;
+    if (A.xcd_stride > 1) {  // see launch_plain: only workgroups on one XCD do work
+        if (b % (unsigned)A.xcd_stride) return;
+        b /= (unsigned)A.xcd_stride;
+    }
+    const int64_t i0 = (int64_t)b * blockDim.x * T + threadIdx.x;
     if (i0 >= A.n) return;
     int64_t ii[T];
     bool act[T];
@@ -798,23 +803,35 @@ __global__ void k_queue_reset(int32_t *head) {
 // batches are throughput bound: the per-lane branch (fewer transcendental ops; other waves
 // hide its scalar instructions).
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8), each XCD with its
+// own L2 and 32 CUs.  A launch of at most 32 workgroups is issue-latency bound on as many CUs
+// wherever it runs, so it is dispatched as 8x the workgroups of which every 8th works: all the
+// working ones then sit on one XCD and read the trajectories' shared data (the target window,
+// the drive and lock-in tables) through one L2 instead of eight.
+constexpr int kXcds = 8;
+constexpr int kCusPerXcd = 32;
+
 // Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
 template <int LAW, int NM, bool MIXED>
-hipError_t launch_plain(const FwdArgs &a, const KConst &K, FwdShape sh, hipStream_t s) {
+hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
-    const int64_t per_block = (int64_t)sh.block * sh.tpl;
-    const dim3 grid((unsigned)((a.n + per_block - 1) / per_block)), blk((unsigned)sh.block);
-    const bool large = branchy && a.n >= kSmallBatch;
+    const dim3 blk((unsigned)sh.block);
+    const bool large = branchy && a0.n >= kSmallBatch;
     if constexpr (NM > 1) {
         if (sh.tpl == 0) {  // mode-parallel: G lanes per trajectory
             constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
             const int64_t per = sh.block / G;
-            const dim3 g2((unsigned)((a.n + per - 1) / per));
-            if (large) hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmBranch>), g2, blk, 0, s, a, K);
-            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree>), g2, blk, 0, s, a, K);
+            const dim3 g2((unsigned)((a0.n + per - 1) / per));
+            if (large) hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmBranch>), g2, blk, 0, s, a0, K);
+            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree>), g2, blk, 0, s, a0, K);
             return hipGetLastError();
         }
     }
+    const int64_t per_block = (int64_t)sh.block * sh.tpl;
+    const int64_t nb = (a0.n + per_block - 1) / per_block;
+    FwdArgs a = a0;
+    a.xcd_stride = nb <= kCusPerXcd ? kXcds : 1;
+    const dim3 grid((unsigned)(nb * a.xcd_stride));
     if constexpr (NM == 1) {
         if (sh.tpl == 2) {
             if (large) hipLaunchKernelGGL((k_forward<LAW, NM, MIXED, kFmBranch, 2>), grid, blk, 0, s, a, K);
