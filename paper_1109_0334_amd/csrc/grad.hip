@@ -187,13 +187,22 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
         dv = DriveP<R>(p, K, NM);
         dgr = DriveGrad(p, K, NM);
     }
-    // drive terms of global step n at t_n, t_n + h/2, t_n + h: the table's or this lane's own
-    auto drive3 = [&](int64_t n, int s, R &d0, R &d1, R &d2) {
+    // drive terms of global step n at t_n, t_n + h/2, t_n + h: the table's or this lane's own.
+    // DP: `edge` carries the term shared with the neighbouring step (t_n + h of step n is t_n of
+    // step n + 1), so a sweep up (down) evaluates two new terms per step, the same values
+    auto drive3 = [&](int64_t n, int s, R &d0, R &d1, R &d2, R &edge, bool up) {
         if constexpr (DP) {
             const double j = 2.0 * (double)n;
-            d0 = dv.at(j);
             d1 = dv.at(j + 1.0);
-            d2 = dv.at(j + 2.0);
+            if (up) {
+                d0 = edge;
+                d2 = dv.at(j + 2.0);
+                edge = d2;
+            } else {
+                d2 = edge;
+                d0 = dv.at(j);
+                edge = d0;
+            }
         } else {
             d0 = Dt[2 * s];
             d1 = Dt[2 * s + 1];
@@ -226,6 +235,8 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     int32_t st = 0;
     int64_t n = 0;
     int cdn = 0;  // steps to the next checkpoint
+    R edge = R(0);
+    if constexpr (DP) edge = dv.at(0.0);
     for (int c = 0; c < nc && !st; ++c) {
         for (int s = 0; s < N; ++s, ++n) {
             if (cdn == 0) {
@@ -251,7 +262,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
             }
             --cdn;
             R d0, d1, d2;
-            drive3(n, s, d0, d1, d2);
+            drive3(n, s, d0, d1, d2, edge, true);
             rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (n + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
@@ -305,6 +316,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
         }
         // recompute the segment, keeping y_n and dJ/du_{n+1}
         int s = (int)(n0 % N);
+        if constexpr (DP) edge = dv.at(2.0 * (double)n0);
         for (int64_t q = n0; q < n1; ++q) {
             const int64_t k = q - n0;
 #pragma unroll
@@ -319,7 +331,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 }
             }
             R d0, d1, d2;
-            drive3(q, s, d0, d1, d2);
+            drive3(q, s, d0, d1, d2, edge, true);
             rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (q + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
@@ -332,6 +344,11 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
         // walk the segment backwards; a step's four stage contributions are summed in R and
         // flushed to FP64 every step, so the result does not depend on the stride
         s = (int)((n1 - 1) % N);
+        double eedge[3] = {0.0, 0.0, 0.0};
+        if constexpr (DP) {
+            edge = dv.at(2.0 * (double)n1);
+            dgr.at(2.0 * (double)n1, eedge);
+        }
         for (int64_t q = n1 - 1; q >= n0; --q) {
             const int64_t k = q - n0;
             R yx[NM], yv[NM];
@@ -359,7 +376,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
             R gzf = R(0);
             R Db[3] = {R(0), R(0), R(0)};
             R d0, d1, d2;
-            drive3(q, s, d0, d1, d2);
+            drive3(q, s, d0, d1, d2, edge, false);
             reverse_step<NM, L, DP>(law, yx, yv, xb, vb, om2, cd, gn, h, h2, h3, h6, d0, d1, d2,
                                     gsf, gzf, Db);
 #pragma unroll
@@ -370,7 +387,11 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 const double j = 2.0 * (double)q;
                 dgr.at(j, e0);
                 dgr.at(j + 1.0, e1);
-                dgr.at(j + 2.0, e2);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    e2[k] = eedge[k];
+                    eedge[k] = e0[k];
+                }
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
                     gD[k] += (double)Db[0] * e0[k] + (double)Db[1] * e1[k] + (double)Db[2] * e2[k];

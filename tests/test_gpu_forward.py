@@ -289,11 +289,13 @@ def test_steps_per_period_edges_mixed(afm, orc, N):
 
 
 @pytest.mark.parametrize("precision,n,nc", [("mixed", 1000, 60), ("fp64", 333, 40),
-                                            ("mixed", 70000, 24)])
+                                            ("mixed", 3000, 24), ("mixed", 70000, 24)])
 def test_launch_shapes_bit_identical(afm, orc, precision, n, nc):
     """Every launch shape (64 / 128 / 256 lanes x 1 / 2 trajectories per lane) gives the same
     bits as the autotuned launch, on ragged batches (partial workgroups, half-filled lane
-    pairs) below and above the large-batch switch; sampled trajectories match the oracle."""
+    pairs) below and above the large-batch switch; sampled trajectories match the oracle.  At
+    3000 trajectories the shapes with at most 32 workgroups run packed onto one XCD and the
+    others on the plain grid."""
     import torch
 
     c = W.config("c2")
