@@ -189,8 +189,16 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     }
     // drive terms of global step n at t_n, t_n + h/2, t_n + h: the table's or this lane's own.
     // DP: `edge` carries the term shared with the neighbouring step (t_n + h of step n is t_n of
-    // step n + 1), so a sweep up (down) evaluates two new terms per step, the same values
-    auto drive3 = [&](int64_t n, int s, R &d0, R &d1, R &d2, R &edge, bool up) {
+    // step n + 1), so a sweep up (down) evaluates two new terms per step, the same values.
+    // Table: pf holds step n's entries, loaded one step ahead (a lone wave per SIMD has nothing
+    // else to hide a load's latency behind); the call loads those of table step sn into pf.
+    R pf[3] = {R(0), R(0), R(0)};
+    auto tab3 = [&](int s) {
+        pf[0] = Dt[2 * s];
+        pf[1] = Dt[2 * s + 1];
+        pf[2] = Dt[2 * s + 2];
+    };
+    auto drive3 = [&](int64_t n, int sn, R &d0, R &d1, R &d2, R &edge, bool up) {
         if constexpr (DP) {
             const double j = 2.0 * (double)n;
             d1 = dv.at(j + 1.0);
@@ -204,9 +212,10 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 edge = d0;
             }
         } else {
-            d0 = Dt[2 * s];
-            d1 = Dt[2 * s + 1];
-            d2 = Dt[2 * s + 2];
+            d0 = pf[0];
+            d1 = pf[1];
+            d2 = pf[2];
+            tab3(sn);
         }
     };
 
@@ -237,6 +246,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
     int cdn = 0;  // steps to the next checkpoint
     R edge = R(0);
     if constexpr (DP) edge = dv.at(0.0);
+    else tab3(0);
     for (int c = 0; c < nc && !st; ++c) {
         for (int s = 0; s < N; ++s, ++n) {
             if (cdn == 0) {
@@ -262,7 +272,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
             }
             --cdn;
             R d0, d1, d2;
-            drive3(n, s, d0, d1, d2, edge, true);
+            drive3(n, s + 1 == N ? 0 : s + 1, d0, d1, d2, edge, true);
             rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (n + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
@@ -317,6 +327,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
         // recompute the segment, keeping y_n and dJ/du_{n+1}
         int s = (int)(n0 % N);
         if constexpr (DP) edge = dv.at(2.0 * (double)n0);
+        else tab3(s);
         for (int64_t q = n0; q < n1; ++q) {
             const int64_t k = q - n0;
 #pragma unroll
@@ -331,7 +342,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
                 }
             }
             R d0, d1, d2;
-            drive3(q, s, d0, d1, d2, edge, true);
+            drive3(q, s + 1 == N ? 0 : s + 1, d0, d1, d2, edge, true);
             rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, d0, d1, d2);
             if (q + 1 >= first_w) {
                 const double u = sample<NM, COMP>(x, cx, zc);
@@ -348,27 +359,42 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
         if constexpr (DP) {
             edge = dv.at(2.0 * (double)n1);
             dgr.at(2.0 * (double)n1, eedge);
+        } else {
+            tab3(s);
         }
-        for (int64_t q = n1 - 1; q >= n0; --q) {
+        // y_q and dJ/du_{q+1} of step q from the segment buffer, loaded one step ahead
+        R pyx[NM], pyv[NM], pub = R(0);
+        auto seg_load = [&](int64_t q) {
             const int64_t k = q - n0;
-            R yx[NM], yv[NM];
-            if (q + 1 >= first_w) {
-                R ub;
-                if constexpr (MIXED) ub = sg[(k * NB + 2 * NM) * n_lanes + i];
-                else ub = reinterpret_cast<const double *>(sg)[(k * NB + 2 * NM) * n_lanes + i];
-#pragma unroll
-                for (int m = 0; m < NM; ++m) xb[m] += ub;
-            }
 #pragma unroll
             for (int m = 0; m < NM; ++m) {
                 if constexpr (MIXED) {
-                    yx[m] = sg[(k * NB + m) * n_lanes + i];
-                    yv[m] = sg[(k * NB + NM + m) * n_lanes + i];
+                    pyx[m] = sg[(k * NB + m) * n_lanes + i];
+                    pyv[m] = sg[(k * NB + NM + m) * n_lanes + i];
                 } else {
                     const double *sgd = reinterpret_cast<const double *>(sg);
-                    yx[m] = sgd[(k * NB + m) * n_lanes + i];
-                    yv[m] = sgd[(k * NB + NM + m) * n_lanes + i];
+                    pyx[m] = sgd[(k * NB + m) * n_lanes + i];
+                    pyv[m] = sgd[(k * NB + NM + m) * n_lanes + i];
                 }
+            }
+            if (q + 1 >= first_w) {
+                if constexpr (MIXED) pub = sg[(k * NB + 2 * NM) * n_lanes + i];
+                else pub = reinterpret_cast<const double *>(sg)[(k * NB + 2 * NM) * n_lanes + i];
+            }
+        };
+        seg_load(n1 - 1);
+        for (int64_t q = n1 - 1; q >= n0; --q) {
+            R yx[NM], yv[NM];
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                yx[m] = pyx[m];
+                yv[m] = pyv[m];
+            }
+            const R ub = pub;
+            if (q > n0) seg_load(q - 1);
+            if (q + 1 >= first_w) {
+#pragma unroll
+                for (int m = 0; m < NM; ++m) xb[m] += ub;
             }
             R gsf[L::NC];
 #pragma unroll
@@ -376,7 +402,7 @@ __global__ void __launch_bounds__(64) k_grad(const GradArgs A, const KConst K) {
             R gzf = R(0);
             R Db[3] = {R(0), R(0), R(0)};
             R d0, d1, d2;
-            drive3(q, s, d0, d1, d2, edge, false);
+            drive3(q, s == 0 ? N - 1 : s - 1, d0, d1, d2, edge, false);
             reverse_step<NM, L, DP>(law, yx, yv, xb, vb, om2, cd, gn, h, h2, h3, h6, d0, d1, d2,
                                     gsf, gzf, Db);
 #pragma unroll
