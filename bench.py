@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--pixel-steps", type=int, default=2)
     ap.add_argument("--no-more", action="store_true",
                     help="skip the time-to-inversion, gradient and 3-mode legs")
+    ap.add_argument("--gradient-probe", action="store_true",
+                    help="run only the c4 adjoint leg (for profiling the adjoint kernel)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -534,6 +536,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "reps": 3}))
+        return
+    if args.gradient_probe:
+        print(json.dumps(gradient_leg(afm, W, dev)))
         return
     cfg = W.config("c2")
     m = cfg["model"]
