@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
                                      C.c_double, dp, dp, dp, dp, dp, dp, ip]
         L.orc_z_to_theta.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32]
         L.orc_z_to_theta.restype = C.c_double
+        L.orc_dtheta_dz.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.orc_dtheta_dz.restype = C.c_double
         L.orc_misfit_grad.argtypes = [mp, dp, C.c_int32, dp, dp, dp]
         L.orc_misfit_grad.restype = C.c_int
         L.orc_pso_invert.argtypes = [mp, dp, C.c_int32, ip, dp, dp, ip, dp, C.c_int32, C.c_int32,
@@ -365,6 +367,10 @@ class Swarm:
 
 def z_to_theta(z, lo, hi, log_scale) -> float:
     return lib().orc_z_to_theta(float(z), float(lo), float(hi), int(bool(log_scale)))
+
+
+def dtheta_dz(z, lo, hi, log_scale) -> float:
+    return lib().orc_dtheta_dz(float(z), float(lo), float(hi), int(bool(log_scale)))
 
 
 def _free_spec(free):

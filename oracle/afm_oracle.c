@@ -531,8 +531,11 @@ int orc_forward_steady(const orc_model *mo, const double *p, int32_t n_cycles, d
 /* ------------------------------------------------------------------------------------------ */
 
 /* Steady amplitude at the parameters p: integrate period by period from the model's initial
- * condition; after each period take the one-period lock-in amplitude; stop when it changes by
- * less than rtol relative or after max_cycles.  Returns the last one-period amplitude. */
+ * condition; after each period take the stroboscopic point P = (u, u'/wd) at the period's end
+ * (the same drive phase every time) and stop after the first period c with
+ * |P_c - P_{c-1}| < rtol |P_c|, or after max_cycles.  Returns the lock-in amplitude of the last
+ * period.  (A test on the one-period amplitude alone stops too early: the transient rings, and
+ * at an extremum of its envelope the amplitude stands still while the phase still moves.) */
 double orc_steady_amplitude(const orc_model *mo, const double *p, int32_t max_cycles, double rtol,
                             int32_t *cycles_used) {
     orc_derived dv;
@@ -540,7 +543,8 @@ double orc_steady_amplitude(const orc_model *mo, const double *p, int32_t max_cy
     int N = mo->steps_per_cycle;
     double y[2 * ORC_MAX_MODES], *u = (double *)malloc(sizeof(double) * N);
     orc_initial_state(mo, y);
-    double Aprev = -1.0, A = NAN, phi;
+    double A = NAN, phi, Pprev[2], P[2];
+    strobe(&dv, y, Pprev);
     int64_t n = 0;
     int c;
     for (c = 0; c < max_cycles; c++) {
@@ -550,11 +554,13 @@ double orc_steady_amplitude(const orc_model *mo, const double *p, int32_t max_cy
         }
         orc_lockin(u, N, N, 1, &A, &phi);
         if (!isfinite(A)) break;
-        if (Aprev > 0.0 && fabs(A - Aprev) < rtol * A) {
+        strobe(&dv, y, P);
+        if (hypot(P[0] - Pprev[0], P[1] - Pprev[1]) < rtol * hypot(P[0], P[1])) {
             c++;
             break;
         }
-        Aprev = A;
+        Pprev[0] = P[0];
+        Pprev[1] = P[1];
     }
     if (cycles_used) *cycles_used = c;
     free(u);
@@ -744,7 +750,7 @@ double orc_z_to_theta(double z, double lo, double hi, int32_t log_scale) {
 }
 
 /* d theta / d z of the map above. */
-static double dtheta_dz(double z, double lo, double hi, int32_t log_scale) {
+double orc_dtheta_dz(double z, double lo, double hi, int32_t log_scale) {
     if (log_scale) return orc_z_to_theta(z, lo, hi, 1) * (log(hi) - log(lo));
     return hi - lo;
 }
@@ -932,7 +938,7 @@ static double misfit_z(const orc_model *mo, const double *p_fixed, int32_t n_fre
     theta_from_z(p_fixed, np, n_free, idx, lo, hi, logs, z, p);
     if (gz) {
         orc_misfit_grad(mo, p, mo->n_cycles, U, &J, g);
-        for (int32_t j = 0; j < n_free; j++) gz[j] = g[idx[j]] * dtheta_dz(z[j], lo[j], hi[j], logs[j]);
+        for (int32_t j = 0; j < n_free; j++) gz[j] = g[idx[j]] * orc_dtheta_dz(z[j], lo[j], hi[j], logs[j]);
     } else {
         double A, phi;
         orc_forward(mo, p, mo->n_cycles, U, &A, &phi, &J, NULL);
