@@ -49,8 +49,21 @@ def _hipcc() -> str:
     return h
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """An object is stale when it is older than its source, any header or this script."""
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src), os.path.abspath(__file__)]
+    deps += [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    deps += [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def _compile(src: str, verbose: bool, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
@@ -62,11 +75,12 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libafm.so next to this file; returns its path."""
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile the sources and link libafm.so next to this file; returns its path.  force=False
+    recompiles only objects older than their source or any header (a development shortcut)."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, force), SOURCES))
     tmp = LIB + ".tmp"
     r = subprocess.run([_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp],
                        capture_output=True, text=True)
@@ -77,4 +91,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, force="--incremental" not in sys.argv))

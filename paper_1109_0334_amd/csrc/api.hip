@@ -417,7 +417,6 @@ afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params
     const size_t bytes = polish_total_bytes(plan, n, kPolishStride);
     if (plan->pws_bytes < bytes) {
         if (plan->pws) (void)hipFree(plan->pws);
-    if (plan->mws) (void)hipFree(plan->mws);
         plan->pws = nullptr;
         plan->pws_bytes = 0;
         if (hipMalloc(&plan->pws, bytes) != hipSuccess)

@@ -139,3 +139,27 @@ def test_arguments_checked(afm):
         plan.forward_points(th, np.full((1, 3), np.nan))
     r = plan.forward_points(th[:, :0], np.ones((1, 3)))
     assert r["amp"].shape == (1, 0)
+
+
+def test_points_then_polish_then_points_on_one_plan(afm):
+    """The point workspace and the polish workspace are separate plan buffers: growing the
+    polish workspace between two afm_forward_points calls must leave the second call's results
+    equal to the first's, bit for bit, and closing the plan must release each buffer once."""
+    import torch
+
+    c, m = _kv3(n_cycles=12, lockin=4)
+    base, free = W.full_params(c), W.free_index(c)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    th = torch.tensor(W.draw_free(c, 64, 25).T.copy(), device="cuda")
+    w = np.random.default_rng(8).uniform(-1.0, 1.0, (2, 3))
+    first = plan.forward_points(th, w, trace=True)
+    first = {k: v.cpu().numpy() for k, v in first.items()}
+    U = plan.forward_batch(th[:, :1], trace=True)["trace"]
+    for n in (4, 96):  # the second polish grows its workspace
+        z = torch.tensor(np.random.default_rng(n).uniform(0.2, 0.8, (len(free), n)), device="cuda")
+        plan.polish(z, U, steps=2)
+    second = plan.forward_points(th, w, trace=True)
+    torch.cuda.synchronize()
+    for k in ("amp", "phase", "status", "trace"):
+        assert np.array_equal(second[k].cpu().numpy().view(np.uint8), first[k].view(np.uint8)), k
+    plan.close()

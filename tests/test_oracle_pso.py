@@ -93,7 +93,7 @@ def test_noiseless_recovery_tiny_swarm_and_lbfgs(orc):
     for seed in (0, 1, 2):
         res = orc.pso_invert(m, ptrue, free, U, P=8, T=10, seed=seed, cutoff=1e-3)
         assert np.all(np.diff(res["hist"]) <= 0)
-        z, J = orc.lbfgs(m, ptrue, free, U, res["z"], 25)
+        z, J = orc.lbfgs(m, ptrue, free, U, res["z"], 40)
         theta = [orc.z_to_theta(z[j], *free[j][1:]) for j in range(len(free))]
         assert J < 1e-20
         assert abs(theta[0] / ptrue[1] - 1) < 1e-6 and abs(theta[1] / ptrue[2] - 1) < 1e-6
