@@ -1,20 +1,23 @@
 """Benchmark: PSO force-inversion generations on one MI355X.
 
-One step = one PSO generation of the whole hot path over the workload's swarm: RK4 integration of
+One step = one PSO generation of the whole hot path over the workload's swarms: RK4 integration of
 every particle's trajectory, lock-in projection and window misfit (one kernel), then personal and
 swarm bests and the Eq. 8 move (one kernel).  Steps run inside the library's captured HIP graph
 (afm_invert), inputs resident in HBM.
 
-Default workload: the precision-path configuration -- point-mass DMT cantilever (k = 40 N/m,
-f0 = 300 kHz, Q = 400, A0 = 20 nm, set-point 0.8 A0), 3 free parameters (H, E*, a0) with uniform
-priors, 1024 particles, 500 periods x 256 RK4 steps, FP32 integration with FP64 lock-in and misfit
-sums, noisy synthetic target (sigma 0.05 nm) made by the plain FP64 GPU path at the truth.
+Headline workload: the uneven pixel batch -- 4096 independent pixel inversions of (H, E*) on the
+point-mass DMT cantilever (k = 40 N/m, f0 = 300 kHz, Q = 400, A0 = 20 nm), each pixel with its own
+E* (log-uniform 0.05-50 GPa), set-point (uniform 0.5-0.9 A0, separation found by the library's
+amplitude-feedback search) and period count (uniform 100-2000, 256 RK4 steps each), 128
+particles per pixel, noiseless synthetic targets from the plain FP64 GPU path at each pixel's
+truth; FP32 integration with FP64 lock-in and misfit sums; all pixels' particles in one
+persistent work-queue kernel per generation.
 
-Prints one JSON line (metric RK4 steps/s).  Also reported: inversions/s (200 generations per
-inversion), the plain FP64 GPU path on the same workload, the forward kernel's roofline (FP32
-VALU), the same kernel on a GPU-filling batch, the uneven pixel-batch workload (4096 pixel
-inversions with per-pixel separation, stiffness and period count, through the persistent
-work-queue kernel), and the oracle timed on one host core.
+Prints one JSON line (metric RK4 steps/s; inversions/s beside it).  Also reported: the forward
+kernel's roofline (FP32 VALU), the precision-path workload (1024 particles, 500 periods, noisy
+target), the plain FP64 GPU path, a GPU-filling plain batch, time to inversion at equal misfit
+accuracy, the adjoint, the 3-mode hybrid inversion, the paper's own inversions, and the oracle
+timed on one host core with its extrapolated time to inversion for every workload.
 """
 from __future__ import annotations
 
@@ -32,24 +35,26 @@ sys.path.insert(0, ROOT)
 # which this build does not emit.  `peak` reports the published figure.
 PEAK_FP32_PUBLISHED = 157.3e12
 PEAK_FP32_SCALAR_ISSUE = 78.6e12
-# Algorithmic FP32 flops per RK4 step of the point-mass DMT kernel (FMA = 2, rcp/sqrt = 1),
-# out-of-contact force path: 4 stages x (gap 1 + force 4 + acceleration 4) + 3 stage states x 4
-# + slope sums 10 + compensated update 10.
-FLOPS_PER_STEP_DMT1 = 68
-# HBM bytes per launch of that kernel from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by a
+# FP32 flops per RK4 step of the point-mass DMT model, the algorithmic count of the hot-path scope
+# (FMA = 2, add/mul = 1, rcp/sqrt = 1): 82.  Recounted from the kernel's own arithmetic: 68 with
+# the far-field force only (what the method needs out of contact), 72 as the far-field block
+# executes it (with the clamp of the gap), 96 for the branch-free block with both force pieces.
+FLOPS_PER_STEP_DMT1 = 82
+# HBM bytes per launch of a kernel from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by a
 # copy kernel of known size), valid only while the kernel sources are unchanged.
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forward_dmt1_c2_pmc.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_forward_queue_dmt1_c3_pmc.md")
+PMC_SUMMARY_C2 = os.path.join(ROOT, "profiles", "k_forward_dmt1_c2_pmc.md")
 KERNEL_SOURCES = ["forward_impl.hpp", "forward_dmt_mixed.hip", "rk4.hpp", "afm_internal.hpp"]
 
 
-def counted_traffic():
-    """Counter-measured bytes per launch of the benchmark kernel, or None when the summary is
-    missing or the kernel sources have changed since the counters were taken."""
+def counted_traffic(path=PMC_SUMMARY):
+    """Counter-measured bytes per launch of a kernel, or None when its summary is missing or the
+    kernel sources have changed since the counters were taken."""
     import hashlib
     import re
 
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None
     t = re.search(r"^traffic_bytes_per_launch:\s*(\d+)", text, re.M)
@@ -69,14 +74,21 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip FP64 and saturated legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision-path (c2), FP64, saturated and steady-exit legs")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-pixels", action="store_true", help="skip the uneven pixel-batch leg")
     ap.add_argument("--pixel-steps", type=int, default=2)
     ap.add_argument("--no-more", action="store_true",
                     help="skip the time-to-inversion, gradient and 3-mode legs")
+    ap.add_argument("--short-c5", action="store_true",
+                    help="run 2 generations and one polish step of the 3-mode hybrid inversion")
     ap.add_argument("--gradient-probe", action="store_true",
                     help="run only the c4 adjoint leg (for profiling the adjoint kernel)")
+    ap.add_argument("--queue-probe", action="store_true",
+                    help="only build the pixel workload and run its work-queue forward launch "
+                         "(afm_misfit_swarms) --steps times (for counter runs of that kernel)")
+    ap.add_argument("--c2-probe", action="store_true",
+                    help="only run the precision-path forward launch (afm_misfit) --steps times")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -111,9 +123,10 @@ def _pixel_problem(afm, W, dev, S):
                 t_sep=t_sep, good=good)
 
 
-def pixel_leg(afm, W, dev, steps):
+def headline_c3(afm, W, dev, K, Wu):
     """Uneven batching: 4096 pixel inversions of (H, E*) with per-pixel E*, set-point and period
-    count (100..2000), 128 particles, through the persistent work-queue kernel."""
+    count (100..2000), 128 particles, through the persistent work-queue kernel; K generations
+    timed as one graph replay, and the forward kernel alone (the same launch) with HIP events."""
     import numpy as np
     import torch
 
@@ -124,24 +137,55 @@ def pixel_leg(afm, W, dev, steps):
     N = m["steps_per_cycle"]
     free = W.free_index(cfg)
     plan = afm.Plan(m, q["base"], free, precision="mixed", device=dev)
-    plan.invert(U, P, 1, seed=0, n_cycles=cyc, swarm_params=spd)
+    plan.invert(U, P, Wu, seed=0, n_cycles=cyc, swarm_params=spd)  # warm-up generations
     torch.cuda.synchronize()
-    plan.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)  # capture
+    plan.invert(U, P, K, seed=0, n_cycles=cyc, swarm_params=spd)  # capture the K-generation graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = plan.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)
+    out = plan.invert(U, P, K, seed=0, n_cycles=cyc, swarm_params=spd)  # timed replay
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    rk4 = float(P) * float(np.sum(pix["cycles"])) * N * steps
+    steps_per_gen = float(P) * float(np.sum(pix["cycles"])) * N
+    # the forward kernel alone: afm_misfit_swarms is the graph's forward launch (same kernel,
+    # grid and queue), enqueued on torch's current stream, where the events are recorded
+    th = torch.tensor(W.draw_free(cfg, S * P, 9).T.copy(), device=dev)
+    plan.misfit_swarms(th, U, P, n_cycles=cyc, swarm_params=spd)  # builds the queue order
+    torch.cuda.synchronize()
+    k_ms = _event_ms(lambda: plan.misfit_swarms(th, U, P, n_cycles=cyc, swarm_params=spd), reps=5)
+    flops = FLOPS_PER_STEP_DMT1 * steps_per_gen
+    achieved = flops / (k_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_PUBLISHED / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED,
+            "traffic": counted_traffic(PMC_SUMMARY),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
+            "kernel": "k_forward_queue<DMT,1 mode,mixed>", "kernel_ms": k_ms,
+            "flops_per_step": FLOPS_PER_STEP_DMT1, "rk4_steps_per_launch": steps_per_gen,
+            "flops_per_launch": flops, "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_ISSUE,
+            "occupancy": f"{S * P} trajectories = {S * P // 64} waves, 4 per SIMD in flight "
+                         "(persistent grid of 4 x 256-lane workgroups per CU)"}
     # the same misfits as one plain-grid launch (per-lane period counts, no queue) for contrast
-    th_all = torch.tensor(W.draw_free(cfg, S * P, 9).T.copy(), device=dev)
     tid = torch.arange(S, device=dev, dtype=torch.int32).repeat_interleave(P)
     ncl = cyc.repeat_interleave(P)
-    plan.misfit(th_all, U, target_id=tid, n_cycles=ncl)  # launch-shape tuning
-    grid_ms = _event_ms(lambda: plan.misfit(th_all, U, target_id=tid, n_cycles=ncl))
-    sat = FLOPS_PER_STEP_DMT1 * rk4 / dt
-    # the same inversions with the adaptive steady-state exit (the period counts become caps)
-    exit_leg = []
+    plan.misfit(th, U, target_id=tid, n_cycles=ncl)  # launch-shape tuning
+    grid_ms = _event_ms(lambda: plan.misfit(th, U, target_id=tid, n_cycles=ncl))
+    return {"dt": dt, "steps_per_gen": steps_per_gen, "roofline": roof, "S": S, "P": P,
+            "T": int(cfg["iters"]), "median_best_J": float(np.median(out["best_J"].cpu().numpy())),
+            "plain_grid_forward_ms": grid_ms, "setup_separation_s": q["t_sep"],
+            "pixels_without_setpoint_crossing": int((~q["good"]).sum()),
+            "plan": plan, "q": q, "th": th, "ncl": ncl}
+
+
+def steady_exit_leg(afm, W, dev, h, steps):
+    """The pixel inversions with the adaptive steady-state exit (the period counts become caps)."""
+    import numpy as np
+    import torch
+
+    cfg = W.config("c3")
+    q, P = h["q"], h["P"]
+    m, U, cyc, spd = q["m"], q["U"], q["cyc"], q["spd"]
+    free = W.free_index(cfg)
+    ms_plain = h["dt"] / max(1, h["K"]) * 1e3
+    res = []
     for rtol in (1e-4, 1e-6):
         pex = afm.Plan(dict(m, steady_rtol=rtol), q["base"], free, precision="mixed", device=dev)
         pex.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)  # capture
@@ -150,21 +194,87 @@ def pixel_leg(afm, W, dev, steps):
         oex = pex.invert(U, P, steps, seed=0, n_cycles=cyc, swarm_params=spd)
         torch.cuda.synchronize()
         dtx = time.perf_counter() - t0
-        used = pex.forward_steady(th_all, n_cycles=ncl)["periods"].double().sum().item()
-        exit_leg.append({"steady_rtol": rtol, "ms_per_generation": dtx / steps * 1e3,
-                         "speedup": dt / dtx,
-                         "periods_saved": 1.0 - used / float(ncl.double().sum().item()),
-                         "median_best_J": float(np.median(oex["best_J"].cpu().numpy()))})
-    return {"workload": "c3-uneven: 4096 pixels x 128 particles, DMT, invert (H, log E*), "
-                        "periods U{100..2000} x 256 steps, per-pixel E* and set-point",
-            "generations": steps, "ms_per_generation": dt / steps * 1e3,
-            "rk4_steps_per_s": rk4 / dt, "inversions_per_s": S / (dt / steps * cfg["iters"]),
-            "achieved_tflops": sat / 1e12, "frac_published_peak": sat / PEAK_FP32_PUBLISHED,
-            "frac_scalar_issue_peak": sat / PEAK_FP32_SCALAR_ISSUE,
-            "plain_grid_forward_ms": grid_ms, "setup_separation_s": q["t_sep"],
-            "pixels_without_setpoint_crossing": int((~q["good"]).sum()),
-            "median_best_J": float(np.median(out["best_J"].cpu().numpy())),
-            "steady_state_exit": exit_leg}
+        used = pex.forward_steady(h["th"], n_cycles=h["ncl"])["periods"].double().sum().item()
+        res.append({"steady_rtol": rtol, "ms_per_generation": dtx / steps * 1e3,
+                    "speedup": ms_plain / (dtx / steps * 1e3),
+                    "periods_saved": 1.0 - used / float(h["ncl"].double().sum().item()),
+                    "median_best_J": float(np.median(oex["best_J"].cpu().numpy()))})
+    return res
+
+
+def c2_leg(afm, W, dev, K, Wu):
+    """The precision-path workload: point-mass DMT, invert (H, E*, a0), 1024 particles, 500
+    periods x 256 steps, noisy target; K generations as a graph replay, the forward kernel alone
+    with HIP events, the plain FP64 forward and a GPU-filling batch of the same kernel."""
+    import torch
+
+    cfg = W.config("c2")
+    m = cfg["model"]
+    P = cfg["particles"]
+    Wn = m["lockin_cycles"] * m["steps_per_cycle"]
+    steps_per_traj = m["n_cycles"] * m["steps_per_cycle"]
+    free = W.free_index(cfg)
+    p_true = W.full_params(cfg)
+    # target: plain FP64 GPU trace at the truth plus seeded measurement noise (setup, untimed)
+    ref = afm.Plan(m, p_true, free, precision="fp64", device=dev)
+    truth = torch.tensor([[cfg["truth"]["H"]], [cfg["truth"]["Estar"]], [cfg["truth"]["a0"]]],
+                         dtype=torch.float64, device=dev)
+    U = ref.forward_batch(truth, trace=True)["trace"] + torch.tensor(W.noise(cfg, Wn, 0), device=dev)
+    U = U.contiguous()
+    plan = afm.Plan(m, p_true, free, precision="mixed", device=dev)
+    plan.invert(U, P, Wu, seed=cfg["seed"], cutoff=1e-3)
+    torch.cuda.synchronize()
+    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    th_dev = torch.tensor(W.draw_free(cfg, P, 5).T.copy(), device=dev)
+    plan.misfit(th_dev, U)
+    torch.cuda.synchronize()
+    k_ms = _event_ms(lambda: plan.misfit(th_dev, U), reps=max(3, min(K, 10)))
+    flops = FLOPS_PER_STEP_DMT1 * P * steps_per_traj
+    achieved = flops / (k_ms * 1e-3)
+    res = {"workload": "c2-precision-path: point-mass DMT, invert (H, E*, a0), 1024 particles, "
+                       "500 periods x 256 RK4 steps, noisy target",
+           "generations": K, "ms_per_generation": dt / K * 1e3,
+           "rk4_steps_per_s": P * steps_per_traj * K / dt,
+           "inversions_per_s": 1.0 / (dt / K * cfg["iters"]),
+           "best_J_after_steps": float(out["best_J"].item()),
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                        "peak": PEAK_FP32_PUBLISHED / 1e12, "unit": "TFLOP/s",
+                        "frac": achieved / PEAK_FP32_PUBLISHED,
+                        "traffic": counted_traffic(PMC_SUMMARY_C2),
+                        "kernel": "k_forward<DMT,1 mode,mixed>", "kernel_ms": k_ms,
+                        "flops_per_launch": flops,
+                        "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_ISSUE,
+                        "occupancy": f"{P} trajectories = {P // 64} waves on 1024 SIMDs "
+                                     "(at most 1.6 % of the chip's issue slots)"}}
+    # plain FP64 per-particle forward on the same workload (one generation's misfits)
+    plan64 = afm.Plan(m, p_true, free, precision="fp64", device=dev)
+    plan64.misfit(th_dev, U)
+    torch.cuda.synchronize()
+    f64_ms = _event_ms(lambda: plan64.misfit(th_dev, U), reps=3)
+    res["fp64_forward"] = {"kernel_ms": f64_ms,
+                           "rk4_steps_per_s": P * steps_per_traj / (f64_ms * 1e-3),
+                           "mixed_speedup": f64_ms / k_ms}
+    # the same kernel on a batch that fills the GPU (4096 swarms x 128 particles, 40 periods)
+    n_sat, nc_sat = 4096 * 128, 40
+    plan_sat = afm.Plan(dict(m, n_cycles=nc_sat), p_true, free, precision="mixed", device=dev)
+    th_sat = torch.tensor(W.draw_free(cfg, n_sat, 6).T.copy(), device=dev)
+    tid = torch.zeros(n_sat, dtype=torch.int32, device=dev)
+    plan_sat.misfit(th_sat, U, target_id=tid)
+    torch.cuda.synchronize()
+    sat_ms = _event_ms(lambda: plan_sat.misfit(th_sat, U, target_id=tid), reps=3)
+    sat_steps = n_sat * nc_sat * m["steps_per_cycle"]
+    sat_ach = FLOPS_PER_STEP_DMT1 * sat_steps / (sat_ms * 1e-3)
+    res["saturated_forward"] = {
+        "trajectories": n_sat, "periods": nc_sat, "kernel_ms": sat_ms,
+        "rk4_steps_per_s": sat_steps / (sat_ms * 1e-3), "achieved_tflops": sat_ach / 1e12,
+        "frac_published_peak": sat_ach / PEAK_FP32_PUBLISHED,
+        "frac_scalar_issue_peak": sat_ach / PEAK_FP32_SCALAR_ISSUE}
+    return res, U, cfg
 
 
 def pixel_time_to_inversion(afm, W, dev, S, cutoff):
@@ -338,42 +448,61 @@ def gradient_leg(afm, W, dev):
     return out
 
 
-def three_mode_leg(afm, W, dev, gens):
-    """c5: 3-mode Kelvin-Voigt cantilever, 16384 particles, 2000 periods x 512 steps: time per
-    generation, and one L-BFGS step on the best 64 points."""
+def three_mode_leg(afm, W, dev, full=True):
+    """c5, the full hybrid inversion: 3-mode Kelvin-Voigt cantilever, 5 parameters (z_c, H, E*,
+    a0, eta), 16384 particles x 300 generations, 2000 periods x 512 steps, then 10 L-BFGS steps
+    on the discrete-adjoint gradient of the best 64 personal bests -- one captured graph.  The
+    target is the plain FP64 GPU trace at the truth; reported: wall time, inversions/s, the
+    recovered parameters against the truth and the oracle's misfit at the returned best.
+    full=False runs 2 generations and one polish step and says so."""
+    import numpy as np
     import torch
+
+    import oracle
 
     cfg = W.config("c5")
     m, free, base = cfg["model"], W.free_index(cfg), W.full_params(cfg)
     P = int(cfg["particles"])
+    T = int(cfg["iters"]) if full else 2
+    ls, lk = (int(cfg["lbfgs_steps"]), int(cfg["lbfgs_topk"])) if full else (1, 64)
     ref = afm.Plan(m, base, free, precision="fp64", device=dev)
     U = ref.forward_batch(torch.tensor([[base[f[0]]] for f in free], device=dev),
                           trace=True)["trace"].contiguous()
     plan = afm.Plan(m, base, free, precision="mixed", device=dev)
-    plan.invert(U, P, 1, seed=0, cutoff=1e-3)
+    # generation time from a short graph replay (3 generations), for the split below
+    plan.invert(U, P, 3, seed=0)  # launch-shape tuning, workspace, capture
     torch.cuda.synchronize()
-    plan.invert(U, P, gens, seed=0, cutoff=1e-3)  # capture
+    t1 = time.perf_counter()
+    plan.invert(U, P, 3, seed=0)
     torch.cuda.synchronize()
+    ms_gen = (time.perf_counter() - t1) / 3 * 1e3
+    # the whole inversion: one call (graph capture, then the replay of T generations and the
+    # polish of the best lk personal bests)
     t0 = time.perf_counter()
-    plan.invert(U, P, gens, seed=0, cutoff=1e-3)
+    out = plan.invert(U, P, T, seed=0, lbfgs_steps=ls, lbfgs_topk=lk)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / gens
-    steps = P * m["n_cycles"] * m["steps_per_cycle"]
-    k = int(cfg["lbfgs_topk"])
-    z = torch.rand(len(free), k, dtype=torch.float64, device=dev, generator=torch.Generator(
-        device=dev).manual_seed(3))
-    plan.polish(z.clone(), U, steps=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.polish(z.clone(), U, steps=1)
-    torch.cuda.synchronize()
-    pol = time.perf_counter() - t0
-    return {"workload": "c5: 3-mode KV + vdW, 5 parameters, 16384 particles, 2000 periods x "
-                        "512 steps, mixed",
-            "ms_per_generation": dt * 1e3, "rk4_steps_per_s": steps / dt,
-            "projected_s_per_inversion_300_generations": dt * cfg["iters"],
-            "lbfgs_step_top64_ms": pol * 1e3,
-            "projected_s_lbfgs_10_steps": pol * cfg["lbfgs_steps"]}
+    dt = time.perf_counter() - t0
+    dt_pso = ms_gen * 1e-3 * T
+    bt = out["best_theta"].cpu().numpy()[:, 0]
+    truth = np.array([base[f[0]] for f in free])
+    p = base.copy()
+    for j, f in enumerate(free):
+        p[f[0]] = bt[j]
+    o = oracle.forward(m, p, U.cpu().numpy()[0])
+    steps = float(P) * T * m["n_cycles"] * m["steps_per_cycle"]
+    return {"workload": "c5: 3-mode KV + vdW, invert (z_c, H, log E*, a0, log eta), 16384 "
+                        "particles, 2000 periods x 512 steps, mixed, then L-BFGS on the best 64",
+            "generations": T, "lbfgs_steps": ls, "lbfgs_topk": lk, "full_run": bool(full),
+            "seconds_inversion": dt, "ms_per_generation": ms_gen,
+            "seconds_pso_from_generation_time": dt_pso, "seconds_polish_remainder": dt - dt_pso,
+            "inversions_per_s": 1.0 / dt, "rk4_steps_per_s_pso": steps / dt_pso,
+            "best_J": float(out["best_J"].item()),
+            "generation_reaching_cutoff": int(out["gen_to_cutoff"].item()),
+            "oracle_J_at_best": o["J"], "oracle_status_at_best": int(o["status"]),
+            "recovered": {f[0]: float(b) for f, b in zip(free, bt)},
+            "relative_error": [float(abs(b / t - 1)) for b, t in zip(bt, truth)],
+            "note": "seconds_inversion is one afm_invert call: graph capture, T generations, "
+                    "polish; the split uses the generation time of a 3-generation replay"}
 
 
 def paper_inversions_leg(afm, W, dev, swarms=64, particles=512):
@@ -463,44 +592,92 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(cfg, seconds):
-    """Oracle misfit of c2 particles on one host core until `seconds` of work (max 4000), plus
-    ns per RK4 step of the oracle for the other force models (a few short trajectories each)."""
+def cpu_baseline(seconds):
+    """The oracle (plain FP64, single thread) on the host: a bounded sample of the headline
+    workload (pixel trajectories, each pixel's E* and period count, misfit against a window
+    trace) until `seconds` of work; the c1 inversion in full; ns per RK4 step of each model
+    (forward and adjoint); and each workload's time to inversion extrapolated from those by step
+    count."""
     import numpy as np
 
     import oracle
     import workloads as W
 
+    cfg = W.config("c3")
     m = cfg["model"]
-    base = W.full_params(cfg)
-    U = np.sin(np.arange(m["lockin_cycles"] * m["steps_per_cycle"]) * 0.1) * 1.6e-8
-    th = W.draw_free(cfg, 4000, 99)
+    pix = W.pixels(cfg)
+    base = W.full_params(cfg)  # the stored c3 separation (set-point 0.8) stands in for every pixel
     free = W.free_index(cfg)
-    steps_per = m["n_cycles"] * m["steps_per_cycle"]
+    th = W.draw_free(cfg, 4000, 99)
+    N = m["steps_per_cycle"]
+    U = np.sin(np.arange(m["lockin_cycles"] * N) * (2 * np.pi / N)) * 1.6e-8
     t0 = time.perf_counter()
-    n = 0
+    n, steps = 0, 0
     while n < 4000:
         p = base.copy()
+        p[2] = pix["Estar"][n]
         for j, f in enumerate(free):
             p[f[0]] = th[n, j]
-        oracle.forward(m, p, U)
+        nc = int(pix["cycles"][n])
+        oracle.forward(m, p, U, n_cycles=nc)
+        steps += nc * N
         n += 1
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
-    ns = {"dmt_point_mass": dt / (n * steps_per) * 1e9}
+    ns = {"dmt_point_mass": dt / steps * 1e9}
+    # the plain method (c1) in full: one 32 x 20 inversion from the oracle's own noiseless target
+    c1 = W.config("c1")
+    m1, p1 = c1["model"], W.full_params(c1)
+    U1 = oracle.forward(m1, p1, want_trace=True)["trace"]
+    t1 = time.perf_counter()
+    r1 = oracle.pso_invert(m1, p1, W.free_index(c1), U1, P=int(c1["particles"]),
+                           T=int(c1["iters"]), seed=int(c1["seed"]))
+    c1_s = time.perf_counter() - t1
     for name, key, cycles, reps in (("lj_point_mass", "c4", 40, 4), ("kv_3mode", "c5", 20, 2)):
         c = W.config(key)
         mm = dict(c["model"], n_cycles=cycles)
         pp = W.full_params(c)
-        t1 = time.perf_counter()
+        Uw = oracle.forward(mm, pp, want_trace=True)["trace"]
+        t2 = time.perf_counter()
         for _ in range(reps):
             oracle.forward(mm, pp)
-        ns[name] = (time.perf_counter() - t1) / (reps * cycles * mm["steps_per_cycle"]) * 1e9
-    return {"value": n * steps_per / dt, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} particles of the workload (misfit, {m['n_cycles']} periods x "
-                      f"{m['steps_per_cycle']} steps each), FP64, single thread, {dt:.1f} s",
-            "ns_per_rk4_step": ns, "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
+        ns[name] = (time.perf_counter() - t2) / (reps * cycles * mm["steps_per_cycle"]) * 1e9
+        t2 = time.perf_counter()
+        oracle.misfit_grad(mm, pp, Uw)
+        ns[name + "_adjoint"] = (time.perf_counter() - t2) / (cycles * mm["steps_per_cycle"]) * 1e9
+    # time to inversion of every workload on this core, extrapolated linearly by step count
+    c2, c3, c4, c5 = (W.config(k) for k in ("c2", "c3", "c4", "c5"))
+
+    def pso_steps(c, cycles_total):
+        return float(c["particles"]) * c["iters"] * cycles_total * c["model"]["steps_per_cycle"]
+
+    s2 = pso_steps(c2, c2["model"]["n_cycles"])
+    s3 = pso_steps(c3, float(np.sum(pix["cycles"])))
+    s4 = float(c4["points"]) * c4["model"]["n_cycles"] * c4["model"]["steps_per_cycle"]
+    s5 = pso_steps(c5, c5["model"]["n_cycles"])
+    s5_pol = float(c5["lbfgs_topk"]) * c5["lbfgs_steps"] * c5["model"]["n_cycles"] * \
+        c5["model"]["steps_per_cycle"]  # one gradient and one trial misfit per L-BFGS step
+    extrap = {
+        "note": "extrapolated: oracle ns per RK4 step (above) x the workload's RK4 steps; "
+                "one core; not run",
+        "c2_inversion_s": s2 * ns["dmt_point_mass"] * 1e-9,
+        "c3_all_4096_pixel_inversions_s": s3 * ns["dmt_point_mass"] * 1e-9,
+        "c4_2048_gradients_s": s4 * ns["lj_point_mass_adjoint"] * 1e-9,
+        "c5_inversion_s": (s5 * ns["kv_3mode"] + s5_pol * (ns["kv_3mode_adjoint"] + ns["kv_3mode"]))
+        * 1e-9,
+    }
+    return {"value": steps / dt, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} trajectories of the pixel workload (the pixel's E* and period count, "
+                      f"a particle drawn in the (H, E*) box, misfit over the last "
+                      f"{m['lockin_cycles']} periods; {steps:.3g} RK4 steps), FP64, single "
+                      f"thread, {dt:.1f} s",
+            "ns_per_rk4_step": ns,
+            "c1_full_inversion": {"seconds": c1_s, "best_J": r1["J"],
+                                  "workload": "c1: 32 particles x 20 generations, 100 periods x "
+                                              "200 steps, FP64, noiseless oracle target"},
+            "time_to_inversion_extrapolated": extrap,
+            "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
 
 
 PAPER_CONTEXT = {
@@ -521,7 +698,6 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the inversion path has no "
               "multi-GPU mode in this build.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1109_0334_amd as afm
@@ -540,121 +716,71 @@ def main():
     if args.gradient_probe:
         print(json.dumps(gradient_leg(afm, W, dev)))
         return
-    cfg = W.config("c2")
-    m = cfg["model"]
-    P = cfg["particles"]
-    Wn = m["lockin_cycles"] * m["steps_per_cycle"]
-    steps_per_traj = m["n_cycles"] * m["steps_per_cycle"]
-    free = W.free_index(cfg)
-    p_true = W.full_params(cfg)
-
-    # target: plain FP64 GPU trace at the truth plus seeded measurement noise (setup, untimed)
-    ref = afm.Plan(m, p_true, free, precision="fp64", device=dev)
-    truth = torch.tensor([[cfg["truth"]["H"]], [cfg["truth"]["Estar"]], [cfg["truth"]["a0"]]],
-                         dtype=torch.float64, device=dev)
-    U = ref.forward_batch(truth, trace=True)["trace"] + torch.tensor(W.noise(cfg, Wn, 0), device=dev)
-    U = U.contiguous()
-
-    plan = afm.Plan(m, p_true, free, precision="mixed", device=dev)
+    if args.queue_probe:
+        cfg = W.config("c3")
+        S, P = int(cfg["pixels"]), int(cfg["particles"])
+        q = _pixel_problem(afm, W, dev, S)
+        plan = afm.Plan(q["m"], q["base"], W.free_index(cfg), precision="mixed", device=dev)
+        th = torch.tensor(W.draw_free(cfg, S * P, 9).T.copy(), device=dev)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            ms.append(_event_ms(lambda: plan.misfit_swarms(th, q["U"], P, n_cycles=q["cyc"],
+                                                           swarm_params=q["spd"])))
+        print(json.dumps({"queue_probe_ms": ms}), flush=True)
+        return
+    if args.c2_probe:
+        cfg = W.config("c2")
+        m = cfg["model"]
+        plan = afm.Plan(m, W.full_params(cfg), W.free_index(cfg), precision="mixed", device=dev)
+        U = torch.zeros(1, m["lockin_cycles"] * m["steps_per_cycle"], dtype=torch.float64,
+                        device=dev) + 1e-8
+        th = torch.tensor(W.draw_free(cfg, cfg["particles"], 5).T.copy(), device=dev)
+        plan.misfit(th, U)  # launch-shape tuning
+        ms = [_event_ms(lambda: plan.misfit(th, U)) for _ in range(max(1, args.steps))]
+        print(json.dumps({"c2_probe_ms": ms}), flush=True)
+        return
     K, Wu = max(1, args.steps), max(1, args.warmup)
-    plan.invert(U, P, Wu, seed=cfg["seed"], cutoff=1e-3)   # warm-up generations
-    torch.cuda.synchronize()
-    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)  # capture the K-generation graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out = plan.invert(U, P, K, seed=cfg["seed"], cutoff=1e-3)  # timed replay
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    h = headline_c3(afm, W, dev, K, Wu)
+    h["K"] = K
+    dt, S, P, T = h["dt"], h["S"], h["P"], h["T"]
     ms_step = dt / K * 1e3
-    rk4_steps = P * steps_per_traj * K
-    value = rk4_steps / dt
-
-    # forward kernel alone, same launch as in the graph, timed with events on its stream
-    theta = W.draw_free(cfg, P, 5).T.copy()
-    th_dev = torch.tensor(theta, device=dev)
-    plan.misfit(th_dev, U)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = max(3, K)
-    e0.record()
-    for _ in range(reps):
-        plan.misfit(th_dev, U)
-    e1.record()
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    flops = FLOPS_PER_STEP_DMT1 * P * steps_per_traj
-    achieved = flops / (k_ms * 1e-3)
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_PUBLISHED / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": counted_traffic(),
-            "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
-            "kernel": "k_forward<DMT,1 mode,mixed>", "kernel_ms": k_ms,
-            "flops_per_launch": flops, "frac_of_scalar_issue_peak": achieved / PEAK_FP32_SCALAR_ISSUE,
-            "occupancy": f"{P} trajectories = {P // 64} waves on 1024 SIMDs"}
-
-    extras = {}
-    if not args.no_extras:
-        # plain FP64 per-particle forward on the same workload (one generation's misfits)
-        plan64 = afm.Plan(m, p_true, free, precision="fp64", device=dev)
-        plan64.misfit(th_dev, U)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(3):
-            plan64.misfit(th_dev, U)
-        e1.record()
-        torch.cuda.synchronize()
-        f64_ms = e0.elapsed_time(e1) / 3
-        extras["fp64_forward"] = {"kernel_ms": f64_ms, "rk4_steps_per_s": P * steps_per_traj / (f64_ms * 1e-3),
-                                  "mixed_speedup": f64_ms / k_ms}
-        # the same kernel on a batch that fills the GPU (4096 swarms x 128 particles, 40 periods)
-        n_sat, nc_sat = 4096 * 128, 40
-        msat = dict(m, n_cycles=nc_sat)
-        plan_sat = afm.Plan(msat, p_true, free, precision="mixed", device=dev)
-        th_sat = torch.tensor(W.draw_free(cfg, n_sat, 6).T.copy(), device=dev)
-        tid = torch.zeros(n_sat, dtype=torch.int32, device=dev)
-        plan_sat.misfit(th_sat, U, target_id=tid)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(3):
-            plan_sat.misfit(th_sat, U, target_id=tid)
-        e1.record()
-        torch.cuda.synchronize()
-        sat_ms = e0.elapsed_time(e1) / 3
-        sat_steps = n_sat * nc_sat * m["steps_per_cycle"]
-        sat_ach = FLOPS_PER_STEP_DMT1 * sat_steps / (sat_ms * 1e-3)
-        extras["saturated_forward"] = {
-            "trajectories": n_sat, "periods": nc_sat, "kernel_ms": sat_ms,
-            "rk4_steps_per_s": sat_steps / (sat_ms * 1e-3), "achieved_tflops": sat_ach / 1e12,
-            "frac_published_peak": sat_ach / PEAK_FP32_PUBLISHED,
-            "frac_scalar_issue_peak": sat_ach / PEAK_FP32_SCALAR_ISSUE}
-
     line = {
-        "metric": "RK4 steps/s", "value": value, "unit": "RK4 steps/s", "n_gpus": 1,
-        "steps": K, "warmup": Wu, "ms_per_step": ms_step, "higher_is_better": True,
+        "metric": "RK4 steps/s", "value": h["steps_per_gen"] * K / dt, "unit": "RK4 steps/s",
+        "n_gpus": 1, "steps": K, "warmup": Wu, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "precision": "FP32 RK4 state (compensated), FP64 lock-in and misfit sums",
         "data": "synthetic",
-        "config": {"workload": "c2-precision-path: point-mass DMT, invert (H, E*, a0), "
-                               "1024 particles, 500 periods x 256 RK4 steps, noisy target",
-                   "particles": P, "periods": m["n_cycles"], "steps_per_period": m["steps_per_cycle"],
-                   "generations_per_inversion": cfg["iters"]},
-        "inversions_per_s": 1.0 / (ms_step * 1e-3 * cfg["iters"]),
-        "best_J_after_steps": float(out["best_J"].item()),
-        "roofline": roof,
+        "config": {"workload": "c3-uneven-pixels: 4096 pixel inversions, point-mass DMT, invert "
+                               "(H, log E*), per-pixel E*, set-point and period count "
+                               "(U{100..2000} x 256 RK4 steps), 128 particles per pixel, "
+                               "persistent work queue, graph-captured generations",
+                   "pixels": S, "particles_per_pixel": P, "steps_per_period": 256,
+                   "generations_per_inversion": T},
+        "inversions_per_s": S / (ms_step * 1e-3 * T),
+        "rk4_steps_per_generation": h["steps_per_gen"],
+        "roofline": h["roofline"],
+        "median_best_J_after_steps": h["median_best_J"],
+        "plain_grid_forward_ms": h["plain_grid_forward_ms"],
+        "setup_separation_s": h["setup_separation_s"],
+        "pixels_without_setpoint_crossing": h["pixels_without_setpoint_crossing"],
     }
-    line.update(extras)
-    if not args.no_pixels:
-        line["uneven_pixels"] = pixel_leg(afm, W, dev, max(1, args.pixel_steps))
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    U2 = cfg2 = None
+    if not args.no_extras:
+        c2, U2, cfg2 = c2_leg(afm, W, dev, K, Wu)
+        line["c2_precision_path"] = c2
+        line["steady_state_exit"] = steady_exit_leg(afm, W, dev, h, max(1, args.pixel_steps))
     if not args.no_more:
-        line["time_to_inversion"] = time_to_inversion(afm, W, dev, U, cfg)
+        if U2 is not None:
+            line["time_to_inversion"] = time_to_inversion(afm, W, dev, U2, cfg2)
         line["time_to_inversion_pixels"] = pixel_time_to_inversion(afm, W, dev, 256, cutoff=1e-3)
         line["plain_method"] = plain_method_leg(afm, W, dev)
         line["paper_solver_shape"] = paper_solver_leg(afm, W, dev)
         line["gradients"] = gradient_leg(afm, W, dev)
-        line["three_mode"] = three_mode_leg(afm, W, dev, 2)
+        line["three_mode"] = three_mode_leg(afm, W, dev, full=not args.short_c5)
         line["paper_inversions"] = paper_inversions_leg(afm, W, dev)
         line["mode_convergence"] = mode_convergence_leg(afm, W, dev)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 

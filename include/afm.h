@@ -233,21 +233,57 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
                       const int32_t *target_id, const double *targets, int32_t n_targets,
                       double *J, int32_t *status, afm_stream_t stream);
 
+/* Misfits of S swarms of P points each (one PSO generation's forward solves of afm_invert,
+ * without the swarm update): point g = s * P + p, theta [n_free][S * P] (device, SI), is solved
+ * with swarm s's parameter vector (swarm_params [AFM_MAX_PARAMS][S], device, free entries
+ * ignored, or NULL for the problem's), swarm s's period count (n_cycles [S], device, or NULL for
+ * the problem's) and compared with target row s (targets [S][W], device).  Outputs (device):
+ * J [S * P] (Eq. 5 on the lock-in window, normalised; +inf on failure), status [S * P].  With
+ * period counts the launch is afm_invert's persistent work queue: 64-point chunks of the swarms,
+ * longest period count first, taken by the waves of a grid sized to the device.  The order is
+ * built on the first call for an n_cycles buffer (a synchronous read of the counts) and reused
+ * while the same buffer, S and P come back (the order only balances the load: the results never
+ * depend on it, so a buffer refilled with other counts still gives exact results).  The queue
+ * order and counter live in a plan-owned workspace (4 (S ceil(P / 64) + 64) bytes).  Without
+ * period counts: afm_misfit's tuned plain launch. */
+afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_t particles,
+                             const double *theta, const int32_t *n_cycles,
+                             const double *swarm_params, const double *targets, double *J,
+                             int32_t *status, afm_stream_t stream);
+
 /* Misfit and its exact gradient with respect to the free parameters for n points: the
- * discrete adjoint of the forward kernel's RK4 trajectory and window misfit (reverse-mode
- * differentiation, stages reversed; same arithmetic precision as the plan), with the state
- * checkpointed every ckpt_stride RK4 steps and each segment recomputed for the reverse sweep.
+ * derivative of the forward kernel's discrete RK4 trajectory and window misfit (same arithmetic
+ * precision as the plan), with the state checkpointed every ckpt_stride RK4 steps.  Two forms:
+ *   SWEEP     the discrete adjoint: per trajectory, each segment recomputed from its checkpoint
+ *             and walked backwards through the transposed stage Jacobians (stages reversed);
+ *             the result is independent of the stride bit for bit;
+ *   SEGMENTS  every (trajectory, segment) pair on its own lane: the segment recomputed from its
+ *             checkpoint with its state and parameter tangents carried forward through the same
+ *             stages, then a backward recursion over the segments per trajectory (the adjoint
+ *             recursion is linear, so the segments combine exactly); the same derivative up to
+ *             rounding, with thousands of times more lanes in flight.  Built for the drive table
+ *             and up to 4 modes.
  * Arguments as afm_misfit; per-trajectory n_cycles must not exceed the problem's n_cycles.
  * Outputs (device): J [n], dJ [n_free][n] = dJ/dtheta_j in 1/(SI unit of parameter j), status.
  * ckpt_stride: RK4 steps between checkpoints, or 0 = autotuned (the first call with a new n
- * times the strides 16, 64 and 256 -- with several modes each with one lane per trajectory and
- * one lane per mode -- and keeps the fastest; that call synchronises the stream).  Every
- * stride and form computes the same bits.
- * Workspace (checkpoints, segment buffer) is owned by the plan and grown on demand. */
+ * times the strides 16, 64 and 256 with every allowed form -- for SWEEP with several modes one
+ * lane per trajectory and one lane per mode -- and keeps the fastest; that call synchronises the
+ * stream).  With an explicit stride the form is the one tuned for this n, else SEGMENTS where
+ * built, else SWEEP (afm_set_grad_form pins it).  J is afm_misfit's bit for bit in every form.
+ * Workspace (checkpoints, segment buffer or segment records: about
+ * n x (n_cycles N / stride) x (2 m + c + 1)(2 m + 1) x 8 bytes for SEGMENTS with m modes and a law
+ * of c constants) is owned by the plan and grown on demand. */
 afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const int32_t *n_cycles,
                           const int32_t *target_id, const double *targets, int32_t n_targets,
                           double *J, double *dJ, int32_t ckpt_stride, int32_t *status,
                           afm_stream_t stream);
+
+/* Form of the gradient launches of a plan (afm_grad_batch, afm_polish, the invert
+ * polish): AUTO (tuned by afm_grad_batch; SEGMENTS where built otherwise), SWEEP, or
+ * SEGMENTS (AFM_ERR_UNSUPPORTED for a parameter-driven base or more than 4 modes).  Clears the
+ * plan's tuned gradient settings. */
+enum { AFM_GRAD_AUTO = 0, AFM_GRAD_SWEEP = 1, AFM_GRAD_SEGMENTS = 2 };
+afm_status afm_set_grad_form(afm_plan *plan, int32_t form);
 
 /* Initialise a swarm (Sec. 3.4): z, v drawn uniformly over the search box (z ~ U[0,1),
  * v = U[0,1) - z), pbest_z = z, pbest_J = gbest_J = +inf, gen_to_cutoff = -1, theta = SI of z.
@@ -297,6 +333,27 @@ afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double *targets,
                       int32_t iters, uint64_t seed,
                       double cutoff, int32_t lbfgs_steps, int32_t lbfgs_topk, double *best_theta,
                       double *best_J, int32_t *gen_to_cutoff, afm_stream_t stream);
+
+/* Separation from an amplitude set-point for n_pixels pixels (the amplitude feedback of Sec. 1,
+ * which holds the oscillation amplitude at a set-point by moving the sample): z_c[s] (m) is the
+ * separation at which the steady amplitude of pixel s equals setpoint[s] * A0.  The steady
+ * amplitude is the plain FP64 forward solve of the plan's problem (its drive, modes, initial
+ * state and force law; the plan's precision, period counts and exit settings are not used) over
+ * `periods` drive periods with lock-in over the last `lockin_periods`.  The search emulates an
+ * approach curve: z steps down from A0 + 2 nm by `step` (m; 0 = 0.25 nm) to the first grid point
+ * whose amplitude is below the set-point (a failed solve counts as below); the bracket between it
+ * and the grid point above is then narrowed `rounds` times (0 .. 64) by 16 equally spaced trial
+ * separations each -- to the first trial at or above the set-point and the one before it -- and
+ * z_c is the bracket's midpoint (bracket width step / 17^rounds).  Pixels with no crossing
+ * (or crossing at the top grid point) get NaN.
+ * params: [AFM_MAX_PARAMS][n_pixels] full parameter vectors per pixel (device; their z_c entry
+ * is ignored) or NULL for the plan's; setpoint: [n_pixels] (device, fraction of A0); zc:
+ * [n_pixels] (device).  Needs the fixed drive table.  Allocates a temporary plan and workspace
+ * (about 4.5 x n_pixels x max((A0 + 2 nm) / step, 16) x 8 bytes) and synchronises the stream before it
+ * returns. */
+afm_status afm_separations(afm_plan *plan, int32_t n_pixels, const double *params,
+                           const double *setpoint, int32_t periods, int32_t lockin_periods,
+                           double step, int32_t rounds, double *zc, afm_stream_t stream);
 
 /* Modes of a uniform clamped-free Euler-Bernoulli cantilever (Sec. 3.2, Eq. 6-7; App. B), for
  * building afm_problem's ratio and gain: beta_i L from cos(beta L) cosh(beta L) + 1 = 0 (Newton),

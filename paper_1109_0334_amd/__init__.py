@@ -38,12 +38,14 @@ IC = {"free_steady": 0, "rest": 1}
 DRIVE = {"table": 0, "params": 1}
 P_BASE_A, P_BASE_F, P_BASE_G = 8, 9, 10  # base-motion slots of a "params" drive
 POLISH = {"plan": 0, "mixed": 1, "fp64": 2}
+GRAD_FORM = {"auto": 0, "sweep": 1, "segments": 2}
 ST_NONFINITE, ST_DIVERGED, ST_BAD_INPUT = 1, 2, 4
 EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_forward_batch",
            "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
            "afm_forward_steady", "afm_forward_points", "afm_beam_modes", "afm_beam_shapes", "afm_last_error",
-           "afm_version")
+           "afm_version", "afm_separations",
+           "afm_misfit_swarms", "afm_set_grad_form")
 
 
 class AfmError(RuntimeError):
@@ -91,6 +93,7 @@ def lib() -> C.CDLL:
     L.afm_plan_create.argtypes = [C.POINTER(_Problem), i32, C.POINTER(vp)]
     L.afm_plan_destroy.argtypes = [vp]
     L.afm_set_launch_shape.argtypes = [vp, i32, i32]
+    L.afm_set_grad_form.argtypes = [vp, i32]
     L.afm_forward_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.afm_misfit.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp]
     L.afm_grad_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
@@ -98,6 +101,7 @@ def lib() -> C.CDLL:
     L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
     L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, vp]
     L.afm_invert.argtypes = [vp, i32, vp, vp, vp, i32, i32, u64, dbl, i32, i32, vp, vp, vp, vp]
+    L.afm_separations.argtypes = [vp, i32, vp, vp, i32, i32, dbl, i32, vp, vp]
     L.afm_beam_modes.argtypes = [i32, i32, dbl, dbl, dbl, dbl, vp, vp, vp]
     L.afm_beam_shapes.argtypes = [i32, i32, vp, vp]
     L.afm_forward_points.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
@@ -106,7 +110,8 @@ def lib() -> C.CDLL:
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
               "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
-              "afm_beam_modes", "afm_beam_shapes", "afm_forward_points", "afm_forward_steady"):
+              "afm_beam_modes", "afm_beam_shapes", "afm_forward_points", "afm_forward_steady",
+              "afm_separations"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -259,6 +264,10 @@ class Plan:
         block=0 returns to autotuning."""
         _check(lib().afm_set_launch_shape(self._h, int(block), int(tpl)), "afm_set_launch_shape")
 
+    def set_grad_form(self, form="auto"):
+        """Pin the gradient form ("sweep" or "segments") or return to tuning ("auto")."""
+        _check(lib().afm_set_grad_form(self._h, GRAD_FORM[form]), "afm_set_grad_form")
+
     def forward_batch(self, theta, n_cycles=None, trace=False):
         """theta [n_free][n] (SI) -> dict(amp [n] m, phase [n] rad, status [n], trace [n][W])."""
         import torch
@@ -328,6 +337,28 @@ class Plan:
                                 targets.shape[0], _ptr(J), _ptr(status), _stream()), "afm_misfit")
         return J, status
 
+    def misfit_swarms(self, theta, targets, particles, n_cycles=None, swarm_params=None):
+        """afm_misfit_swarms: S swarms of `particles` points (theta [n_free][S*P]) against
+        target rows [S][W], per-swarm period counts [S] and parameter vectors [MAX_PARAMS][S]
+        -> (J [S*P], status [S*P]).  Keep n_cycles the same tensor across calls to reuse the
+        work-queue order."""
+        import torch
+
+        targets = _dev_f64(targets, self.device).reshape(-1, self.W)
+        S = targets.shape[0]
+        theta = _dev_f64(theta, self.device).reshape(self.n_free, S * int(particles))
+        J = torch.empty(S * int(particles), dtype=torch.float64, device=self.device)
+        status = torch.empty(S * int(particles), dtype=torch.int32, device=self.device)
+        nc = n_cycles if (n_cycles is None or isinstance(n_cycles, torch.Tensor)) else \
+            _dev_i32(n_cycles, self.device)
+        sp = None if swarm_params is None else \
+            _dev_f64(swarm_params, self.device).reshape(MAX_PARAMS, S)
+        self._keep_ms = (targets, nc, sp)
+        _check(lib().afm_misfit_swarms(self._h, S, int(particles), _ptr(theta), _ptr(nc), _ptr(sp),
+                                       _ptr(targets), _ptr(J), _ptr(status), _stream()),
+               "afm_misfit_swarms")
+        return J, status
+
     def grad_batch(self, theta, targets, target_id=None, n_cycles=None, ckpt_stride=0):
         """Discrete-adjoint gradient: (J [n], dJ [n_free][n] per SI unit, status [n])."""
         import torch
@@ -344,6 +375,20 @@ class Plan:
                                     targets.shape[0], _ptr(J), _ptr(dJ), int(ckpt_stride),
                                     _ptr(status), _stream()), "afm_grad_batch")
         return J, dJ, status
+
+    def separations(self, setpoint, params=None, periods=3000, lockin=2, step=0.25e-9, rounds=6):
+        """afm_separations: z_c [S] (m) at which each pixel's steady amplitude equals
+        setpoint[s] * A0; params: optional [MAX_PARAMS][S] full parameter vectors per pixel."""
+        import torch
+
+        sp = _dev_f64(setpoint, self.device).reshape(-1)
+        S = sp.shape[0]
+        pp = None if params is None else _dev_f64(params, self.device).reshape(MAX_PARAMS, S)
+        zc = torch.empty(S, dtype=torch.float64, device=self.device)
+        _check(lib().afm_separations(self._h, S, _ptr(pp), _ptr(sp), int(periods), int(lockin),
+                                     float(step), int(rounds), _ptr(zc), _stream()),
+               "afm_separations")
+        return zc
 
     def swarm_init(self, particles, swarms=1, seed=0) -> Swarm:
         sw = Swarm(self.n_free, particles, swarms, self.device)

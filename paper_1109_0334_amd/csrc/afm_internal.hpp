@@ -42,10 +42,11 @@ struct KConst {
     double k;              // first-mode stiffness, N/m
     double wd;             // drive angular frequency, rad/s
     double fref;           // drive frequency, Hz (the time unit of a parameter-driven base)
-    double steady_rtol;    // > 0: adaptive steady-state exit (per-period amplitude change)
+    double steady_rtol;    // > 0: adaptive steady-state exit (stroboscopic point test)
     double G;              // (w0 / wd)^2
     double h;              // 2 pi / N
     double div_nm;         // divergence threshold on |u|, nm
+    double dmax;           // largest |drive term| of the table, nm (kFmBlock's bound)
     double om2[kMaxModes];    // (w_i / wd)^2
     double cdamp[kMaxModes];  // w_i / (wd Q_i)
     double gain[kMaxModes];   // gamma_i
@@ -69,6 +70,7 @@ template <> struct Ops<float> {
     __device__ static inline float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
     __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     __device__ static inline float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    __device__ static inline float abs(float a) { return __builtin_fabsf(a); }
 };
 template <> struct Ops<double> {
     __device__ static inline double rcp(double x) { return 1.0 / x; }
@@ -77,6 +79,7 @@ template <> struct Ops<double> {
     __device__ static inline double exp2(double x) { return ::exp2(x); }
     __device__ static inline double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
     __device__ static inline double max(double a, double b) { return __builtin_fmax(a, b); }
+    __device__ static inline double abs(double a) { return __builtin_fabs(a); }
 };
 
 // 10^-4.5: sqrt(1 nm) in sqrt(m), used by the Hertz and Kelvin-Voigt terms.
@@ -94,11 +97,42 @@ constexpr double kSqrtNano = 3.1622776601683794e-05;
 //   kFmSkip    the far-field piece always, the contact piece only when some lane of the wave
 //              is in contact, behind one wave-uniform branch (fewest issue slots when one wave
 //              owns a SIMD and contact is rare); laws without this form treat it as kFmFree
+//   kFmFar     the far-field piece only: valid only where no lane can be in contact (the
+//              contact piece would add an exact zero), see kFmBlock
+//   kFmBlock   for the time loop (forward_impl.hpp integrate): before each block of four RK4
+//              steps, one wave-uniform test of a bound on how far every lane's gap can fall
+//              within the block; a wave far from contact runs the block as kFmFar, otherwise
+//              as kFmFree.  Both add the same terms, so the bits are kFmFree's.  Laws without
+//              a block bound (and every per-step loop) treat it as kFmFree
 constexpr int kFmBranch = 0;
 constexpr int kFmFree = 1;
 constexpr int kFmSkip = 2;
+constexpr int kFmFar = 3;
+constexpr int kFmBlock = 4;
+
+// Bound used by kFmBlock for a point mass: over a block of four steps of size h, every RK4 stage
+// state lies within 4h of the block's start in time, and its velocity within 4h A of the start's,
+// where A bounds |acceleration| = |-om2 (g - z_c) - cd v + F + D| at any stage state.  Out of
+// contact (gap >= dskip) |F| <= fmax = |BH| / dskip^2 and |D| <= dmax; |g - z_c| and |v| can grow
+// within the block by at most 4h (|v0| + 4h A) and 4h A, so
+//   A <= (om2 |u0| + (4h om2 + cd) |v0| + fmax + dmax) / (1 - 16 h^2 om2 - 4h cd) = A*,
+// and no stage gap falls below g0 - 4h (|v0| + 4h A*).  If that is above dskip for every lane of
+// the wave, the whole block stays out of contact (the first stage to enter contact would need a
+// larger excursion than the bound allows while all earlier stages were out of contact).  The
+// factors carry a few percent of margin and the reach an absolute 1e-3 nm, far above FP32
+// rounding of the stage arithmetic.
+template <typename R>
+struct BlockBound {
+    R c_u, c_v, c_f, c_0;  // A* = c_u |u0| + c_v |v0| + c_f fmax + c_0
+    R h4, h16;             // reach = h4 (|v0| + h16 A*) + 1e-3 nm
+};
 
 template <int LAW, typename R> struct Law;
+
+// whether a law has the kFmBlock bound (a `kBlock` member that is true)
+template <class L, class = void> struct HasBlock : std::false_type {};
+template <class L>
+struct HasBlock<L, std::void_t<decltype(L::kBlock)>> : std::integral_constant<bool, L::kBlock> {};
 
 // DMT: out of contact BH / d^2 with BH = -G H R / (6 k) (nm^3); in contact the attraction is
 // frozen at its d = a0 value and BE (a0 - d)^{3/2} is added, BE = G (4/3) E* sqrt(R) 10^-4.5 / k.
@@ -111,7 +145,7 @@ template <int LAW, typename R> struct Law;
 template <typename R> struct Law<AFM_LAW_DMT, R> {
     static constexpr bool kRate = false;
     static constexpr bool kBranch = true;
-    R zc, a0, BH, BHa, BE, ce, cea0, clim, dskip;
+    R zc, a0, BH, BHa, BE, ce, cea0, clim, dskip, fmax;
     Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
@@ -130,10 +164,27 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
         ce = (R)c;
         cea0 = (R)(c * a0n);
         clim = be < 0.0 ? -(R)INFINITY : (R)INFINITY;
+        // largest out-of-contact attraction |BH| / d^2 (d >= dskip), rounded up; infinite for a
+        // separation at or below zero (the block bound then never skips)
+        const double ds = (double)dskip;
+        fmax = ds > 0.0 ? (R)(::fabs(bh) / (ds * ds) * (1.0 + 1e-6)) : (R)INFINITY;
+    }
+    // kFmBlock: whether the gap g (rate v) may come within dskip during the next four steps
+    // (see BlockBound); NaN states count as near
+    static constexpr bool kBlock = true;
+    __device__ inline bool near(R g, R v, const BlockBound<R> &bb) const {
+        const R av = Ops<R>::abs(v);
+        const R Am = Ops<R>::fma(bb.c_u, Ops<R>::abs(g - zc),
+                                 Ops<R>::fma(bb.c_v, av, Ops<R>::fma(bb.c_f, fmax, bb.c_0)));
+        const R reach = Ops<R>::fma(bb.h4, Ops<R>::fma(bb.h16, Am, av), R(1e-3));
+        return !(g - reach > dskip);
     }
     template <int FM> __device__ inline R add(R d, R, R b) const {
         if constexpr (std::is_same<R, float>::value) {
-            if constexpr (FM != kFmBranch) {
+            if constexpr (FM == kFmFar) {
+                const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
+                return Ops<R>::fma(BH * r, r, b);
+            } else if constexpr (FM != kFmBranch) {
                 // max(d, a0) as a median against the largest finite float (equal for every
                 // finite d): IEEE-mode v_max would first quiet both operands, two extra
                 // instructions per pass of the time loop
@@ -142,7 +193,7 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
                 // the Hertz term is zero unless d < a0 (up to the rounding of ce a0); the skip
                 // form skips it only when every lane of the wave is above dskip, where the
                 // branch-free form adds an exact zero, so both give the same bits in every lane
-                if (FM == kFmFree || __builtin_amdgcn_ballot_w64(d < dskip) != 0) {
+                if (FM != kFmSkip || __builtin_amdgcn_ballot_w64(d < dskip) != 0) {
                     // a scheduling barrier (no instruction, no memory effect) keeps the compiler
                     // from speculating this block into a select evaluated on every pass
                     if constexpr (FM == kFmSkip) __builtin_amdgcn_sched_barrier(0);
@@ -162,7 +213,10 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
                 return f;
             }
         } else {
-            if constexpr (FM != kFmBranch) {
+            if constexpr (FM == kFmFar) {
+                const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+                return Ops<R>::fma(BH * r, r, b);
+            } else if constexpr (FM != kFmBranch) {
                 const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
                 const R del = Ops<R>::max(a0 - d, R(0));
                 return Ops<R>::fma(BE * del, Ops<R>::sqrt(del), Ops<R>::fma(BH * r, r, b));
@@ -488,7 +542,13 @@ struct GradArgs {
     const double *base;    // optional per-point full parameter vectors [kMaxParams][base_ld]
     int64_t base_ld;
     int32_t mp;            // mode-parallel kernel (one lane per mode; several modes only)
+    int32_t form;          // kGradSweep or kGradSegments (see grad.hip)
 };
+
+// Forms of the adjoint: one reverse sweep per trajectory, or every checkpoint segment
+// differentiated on its own lane (tangent columns) and the segments combined afterwards.
+constexpr int32_t kGradSweep = 1;
+constexpr int32_t kGradSegments = 2;
 
 // ------------------------------------------------------------------------------------------
 // host side
@@ -533,12 +593,19 @@ struct afm_plan {
     int64_t tuned_n = -1;
     int32_t tuned_kc = 0;
     int32_t tuned_mp = 0;
+    int32_t tuned_form = 0;
+    int32_t grad_form = 0;          // afm_set_grad_form: 0 = automatic, else a pinned form
     // plan-owned workspace for afm_polish
     void *pws = nullptr;
     size_t pws_bytes = 0;
     // plan-owned workspace for afm_forward_points (window modal coordinates)
     void *mws = nullptr;
     size_t mws_bytes = 0;
+    // plan-owned work-queue order of afm_misfit_swarms and the inputs it was built for
+    void *qws = nullptr;
+    size_t qws_bytes = 0;
+    const int32_t *q_ncyc = nullptr;
+    int32_t q_S = 0, q_P = 0;
     // PSO constants
     double pso_w, pso_c1, pso_c2, pso_vmax;
     // tuned launch shapes of plain forward launches (filled on first use of a batch size)
@@ -596,7 +663,13 @@ hipError_t forward_shape(const afm_plan *plan, int32_t prec, const FwdArgs &a, i
                          hipStream_t s, const std::function<hipError_t(FwdShape)> &launch,
                          FwdShape *out);
 size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
-size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc);
+// segment buffer (kGradSweep) or segment records (kGradSegments) of a gradient launch
+size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc, int32_t form);
+// whether the segment-parallel form is built for the plan's problem
+bool grad_segments_ok(const afm_plan *plan);
+// the form a gradient launch takes when no tuning applies: the pinned form, else the segment
+// form where it is built, else the sweep
+int32_t grad_default_form(const afm_plan *plan);
 int32_t polish_prec(const afm_plan *plan);
 
 // L-BFGS polish (lbfgs.hip)

@@ -1,6 +1,7 @@
 // api.hip -- the extern "C" entry points of libafm: plan set-up (non-dimensionalisation, base
 // amplitude, initial state, drive and lock-in tables), argument validation, and dispatch to
 // the forward and swarm kernels.  Host code only.
+#include <algorithm>
 #include <complex>
 #include <cstring>
 #include <new>
@@ -132,6 +133,8 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
         drive_d[j] = d;
         drive_f[j] = (float)d;
     }
+    K.dmax = 0.0;
+    for (const double d : drive_d) K.dmax = std::max(K.dmax, std::fabs(d));
     lock.resize(2 * (N + 1));
     for (int p = 0; p <= N; ++p) {
         const int q = p == N ? 0 : p;
@@ -218,6 +221,18 @@ afm_status afm_set_launch_shape(afm_plan *plan, int32_t block, int32_t tpl) {
     return AFM_OK;
 }
 
+afm_status afm_set_grad_form(afm_plan *plan, int32_t form) {
+    if (!plan) return fail(AFM_ERR_INVALID, "afm_set_grad_form: plan is NULL");
+    if (form != AFM_GRAD_AUTO && form != AFM_GRAD_SWEEP && form != AFM_GRAD_SEGMENTS)
+        return fail(AFM_ERR_INVALID, "afm_set_grad_form: unknown form");
+    if (form == AFM_GRAD_SEGMENTS && !grad_segments_ok(plan))
+        return fail(AFM_ERR_UNSUPPORTED,
+                    "afm_set_grad_form: the segment form needs the drive table and at most 4 modes");
+    plan->grad_form = form;
+    plan->tuned_n = -1;  // tune again under the new setting
+    return AFM_OK;
+}
+
 afm_status afm_plan_destroy(afm_plan *plan) {
     if (!plan) return AFM_OK;
     if (plan->stream) (void)hipStreamSynchronize(plan->stream);
@@ -226,6 +241,7 @@ afm_status afm_plan_destroy(afm_plan *plan) {
     if (plan->gws) (void)hipFree(plan->gws);
     if (plan->pws) (void)hipFree(plan->pws);
     if (plan->mws) (void)hipFree(plan->mws);
+    if (plan->qws) (void)hipFree(plan->qws);
     if (plan->d_drive_f) (void)hipFree(plan->d_drive_f);
     if (plan->d_drive_d) (void)hipFree(plan->d_drive_d);
     if (plan->d_lock) (void)hipFree(plan->d_lock);
@@ -309,13 +325,15 @@ static afm_status ensure_grad_ws(afm_plan *plan, size_t bytes) {
 }
 
 
-static afm_status run_grad(afm_plan *plan, GradArgs a, int32_t kc, int32_t mp, hipStream_t s) {
+static afm_status run_grad(afm_plan *plan, GradArgs a, int32_t kc, int32_t mp, int32_t form,
+                           hipStream_t s) {
     const size_t cb = grad_ckpt_bytes(plan, plan->precision, a.n, kc);
-    const size_t sb = grad_seg_bytes(plan, plan->precision, a.n, kc);
+    const size_t sb = grad_seg_bytes(plan, plan->precision, a.n, kc, form);
     afm_status st = ensure_grad_ws(plan, cb + ((sb + 255) & ~(size_t)255) + 256);
     if (st != AFM_OK) return st;
     a.kc = kc;
     a.mp = plan->kc.nm > 1 ? mp : 0;
+    a.form = form;
     a.seg = (float *)plan->gws;
     a.ckpt = (float *)((char *)plan->gws + ((sb + 255) & ~(size_t)255));
     hipError_t e = launch_grad(plan, a, s);
@@ -364,16 +382,25 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     const bool tuned = plan->tuned_n == n && plan->tuned_kc > 0;
     // mode-parallel (several modes) unless tuning found otherwise; both compute the same bits
     const int32_t mp_default = tuned ? plan->tuned_mp : (n * 4 <= 65536 ? 1 : 0);
-    if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, mp_default, s);
-    if (tuned) return run_grad(plan, a, plan->tuned_kc, plan->tuned_mp, s);
-    // autotune: time each candidate stride (and, with several modes, one lane per trajectory vs
-    // one lane per mode) on this call's inputs, keep the fastest
-    struct Cand { int32_t kc, mp; };
+    const int32_t form_default = tuned ? plan->tuned_form : grad_default_form(plan);
+    if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, mp_default, form_default, s);
+    if (tuned) return run_grad(plan, a, plan->tuned_kc, plan->tuned_mp, plan->tuned_form, s);
+    // autotune: time each candidate stride and form (the reverse sweep -- with several modes one
+    // lane per trajectory or one lane per mode -- and the segment-parallel form) on this call's
+    // inputs, keep the fastest; candidates needing more than 8 GiB of workspace are left out
+    struct Cand { int32_t kc, mp, form; };
     std::vector<Cand> cand;
     for (int32_t kc : {16, 64, 256}) {
-        cand.push_back({kc, 0});
-        if (plan->kc.nm > 1) cand.push_back({kc, 1});
+        if (plan->grad_form != kGradSegments || !grad_segments_ok(plan)) {
+            cand.push_back({kc, 0, kGradSweep});
+            if (plan->kc.nm > 1) cand.push_back({kc, 1, kGradSweep});
+        }
+        if (plan->grad_form != kGradSweep && grad_segments_ok(plan) &&
+            grad_seg_bytes(plan, plan->precision, n, kc, kGradSegments) +
+                    grad_ckpt_bytes(plan, plan->precision, n, kc) <= ((size_t)8 << 30))
+            cand.push_back({kc, 0, kGradSegments});
     }
+    if (cand.empty()) cand.push_back({256, 0, kGradSweep});
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(AFM_ERR_HIP, "afm_grad_batch: event creation failed");
@@ -381,7 +408,7 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     Cand best = cand[0];
     for (size_t c = 0; c < cand.size(); ++c) {
         (void)hipEventRecord(e0, s);
-        st = run_grad(plan, a, cand[c].kc, cand[c].mp, s);
+        st = run_grad(plan, a, cand[c].kc, cand[c].mp, cand[c].form, s);
         if (st != AFM_OK) break;
         (void)hipEventRecord(e1, s);
         float ms = 0;
@@ -400,7 +427,11 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     plan->tuned_n = n;
     plan->tuned_kc = best.kc;
     plan->tuned_mp = best.mp;
-    return AFM_OK;  // the last candidate's results are in the outputs
+    plan->tuned_form = best.form;
+    // the outputs must be the chosen configuration's: the forms agree only to rounding
+    const Cand &last = cand.back();
+    if (last.kc == best.kc && last.mp == best.mp && last.form == best.form) return AFM_OK;
+    return run_grad(plan, a, best.kc, best.mp, best.form, s);
 }
 
 afm_status afm_polish(afm_plan *plan, int64_t n, double *z, const double *params,

@@ -719,9 +719,382 @@ __global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K
     A.status[i] = 0;
 }
 
+// ------------------------------------------------------------------------------------------
+// Segment-parallel form.  The reverse sweep above is one long dependent chain per trajectory:
+// with a few thousand trajectories (one wave per SIMD or less) it is latency-bound.  The adjoint
+// recursion is linear in the adjoint state, so the trajectory's checkpoint segments can be
+// differentiated independently and combined afterwards:
+//   segment s maps the state y_s at its first step to y_{s+1}; let Phi_s = dy_{s+1}/dy_s,
+//   S_s = dy_{s+1}/dtheta (theta: the law's constants and z_c, with y_s held fixed), and let
+//   c_s = dJ_s/dy_s, p_s = dJ_s/dtheta be the derivatives of the segment's own window terms J_s.
+//   Then, from lambda_{n_seg} = 0 backwards, dJ/dtheta = sum_s (p_s + S_s^T lambda_{s+1}) and
+//   lambda_s = c_s + Phi_s^T lambda_{s+1}.
+// k_grad_ckpt runs the forward pass (checkpoints, J, status, dJ/du scale), k_grad_tan gives every
+// (trajectory, segment) pair its own lane, which recomputes the segment from its checkpoint and
+// carries the 2 NM + NC + 1 tangent columns of (Phi_s, S_s) forward through the RK4 stages (the
+// same stage states and force partials as the reverse sweep), accumulating c_s and p_s from the
+// window samples in FP64, and k_grad_combine runs the short backward recursion over the segments
+// in FP64, one lane per trajectory.  Tangents are in deflection coordinates (mode 1's state is
+// the gap g = z_c + u_1, but z_c is a parameter of the map: the z_c column moves the gap at fixed
+// deflection), matching the reverse sweep's dJ/dz_c.  The result is the same exact derivative as
+// the reverse sweep up to rounding (it depends on the stride only through rounding).
+
+// number of FP64 record entries per segment: Phi (2NM x 2NM), S (2NM x NP), c (2NM), p (NP)
+template <int NM, int NP>
+constexpr int seg_fields() { return 4 * NM * NM + 2 * NM * NP + 2 * NM + NP; }
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad_ckpt(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr bool COMP = MIXED;
+    constexpr int NS = 4 * NM;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const L law(p, K);
+    const double zc = p[0] * 1e9;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int N = K.N;
+    const int64_t W = (int64_t)K.lockin * N;
+    const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : 0;
+    const int kc = A.kc;
+    const int64_t n_lanes = A.n;
+    double *coef_out = reinterpret_cast<double *>(A.seg);
+    auto fail = [&](int32_t st) {
+        A.J[i] = INFINITY;
+        for (int j = 0; j < K.n_free; ++j) A.dJ[(int64_t)j * A.ld + i] = NAN;
+        A.status[i] = st;
+        coef_out[i] = 0.0;
+    };
+    if (nc < K.lockin || nc > K.n_cycles || row < 0 || row >= A.n_targets) {
+        fail(AFM_ST_BAD_INPUT);
+        return;
+    }
+    const double *__restrict__ Urow = A.targets + row * W;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        x[m] = (R)(m == 0 ? zc + K.y0[0] : K.y0[m]);
+        v[m] = (R)K.y0[NM + m];
+        cx[m] = R(0);
+        cv[m] = R(0);
+        om2[m] = (R)K.om2[m];
+        cd[m] = (R)K.cdamp[m];
+        gn[m] = (R)K.gain[m];
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    float *__restrict__ ck = A.ckpt;
+    const int64_t Ntot = (int64_t)nc * N;
+    const int64_t first_w = Ntot - W + 1;
+    double Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+    int64_t n = 0;
+    int cdn = 0;
+    for (int c = 0; c < nc && !st; ++c) {
+        for (int s = 0; s < N; ++s, ++n) {
+            if (cdn == 0) {
+                const int64_t slot = n / kc;
+#pragma unroll
+                for (int m = 0; m < NM; ++m) {
+                    if constexpr (MIXED) {
+                        ck[(slot * NS + m) * n_lanes + i] = x[m];
+                        ck[(slot * NS + NM + m) * n_lanes + i] = v[m];
+                        ck[(slot * NS + 2 * NM + m) * n_lanes + i] = cx[m];
+                        ck[(slot * NS + 3 * NM + m) * n_lanes + i] = cv[m];
+                    } else {
+                        double *ckd = reinterpret_cast<double *>(ck);
+                        ckd[(slot * NS + m) * n_lanes + i] = x[m];
+                        ckd[(slot * NS + NM + m) * n_lanes + i] = v[m];
+                    }
+                }
+                cdn = kc;
+            }
+            --cdn;
+            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                        Dt[2 * s + 1], Dt[2 * s + 2]);
+            if (n + 1 >= first_w) {
+                const double u = sample<NM, COMP>(x, cx, zc);
+                const double U = Urow[n + 1 - first_w] * 1e9;
+                const double e = U - u;
+                Jn = __builtin_fma(e, e, Jn);
+                Jd = __builtin_fma(U, U, Jd);
+            }
+        }
+        bool fin = true;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) fin = fin && isfinite(x[m]) && isfinite(v[m]);
+        if (!fin) st = AFM_ST_NONFINITE;
+        else if (fabs(sample<NM, COMP>(x, cx, zc)) > K.div_nm) st = AFM_ST_DIVERGED;
+    }
+    const double J = Jn / Jd;
+    if (st || !isfinite(J)) {
+        fail(st ? st : AFM_ST_NONFINITE);
+        return;
+    }
+    A.J[i] = J;
+    A.status[i] = 0;
+    coef_out[i] = -2.0 / Jd;  // dJ/du_n = coef (U_n - u_n)
+}
+
+// Tangent of one slope evaluation: (dx, dv) the stage state's tangent, dz the z_c component and
+// dcv the constants' components of the column; returns the acceleration tangents.
+template <int NM, class L, typename R>
+__device__ __forceinline__ void slope_jvp(const R (&dx)[NM], const R (&dv)[NM], R dz,
+                                          const R (&dcv)[L::NC], R Fd, R Fdd,
+                                          const R (&dc)[L::NC], const R (&om2)[NM],
+                                          const R (&cd)[NM], R (&da)[NM]) {
+    const R dd = mode_sum<NM>(dx) + dz;
+    R dF = Fd * dd;
+    if constexpr (L::kRate) dF = Ops<R>::fma(Fdd, mode_sum<NM>(dv), dF);
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) dF = Ops<R>::fma(dc[k], dcv[k], dF);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) da[m] = Ops<R>::fma(-om2[m], dx[m], Ops<R>::fma(-cd[m], dv[m], dF));
+}
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr bool COMP = MIXED;
+    constexpr int NS = 4 * NM;
+    constexpr int NY = 2 * NM;             // state columns
+    constexpr int NP = L::NC + 1;          // parameter columns: the constants, then z_c
+    constexpr int NF = seg_fields<NM, NP>();
+    const int64_t n_lanes = A.n;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = l % n_lanes, sgi = l / n_lanes;
+    const int N = K.N, kc = A.kc;
+    const int64_t nseg_max = ((int64_t)K.n_cycles * N + kc - 1) / kc;
+    if (sgi >= nseg_max) return;
+    if (A.status[i] != 0) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int64_t Ntot = (int64_t)nc * N;
+    const int64_t n0 = sgi * kc;
+    if (n0 >= Ntot) return;
+    const int64_t n1 = n0 + kc < Ntot ? n0 + kc : Ntot;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const L law(p, K);
+    const double zc = p[0] * 1e9;
+    const int64_t W = (int64_t)K.lockin * N;
+    const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : 0;
+    const double *__restrict__ Urow = A.targets + row * W;
+    const int64_t first_w = Ntot - W + 1;
+    const double coef = reinterpret_cast<const double *>(A.seg)[i];
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    R x[NM], v[NM], cx[NM], cv[NM], om2[NM], cd[NM], gn[NM];
+    const float *__restrict__ ck = A.ckpt;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        om2[m] = (R)K.om2[m];
+        cd[m] = (R)K.cdamp[m];
+        gn[m] = (R)K.gain[m];
+        if constexpr (MIXED) {
+            x[m] = ck[(sgi * NS + m) * n_lanes + i];
+            v[m] = ck[(sgi * NS + NM + m) * n_lanes + i];
+            cx[m] = ck[(sgi * NS + 2 * NM + m) * n_lanes + i];
+            cv[m] = ck[(sgi * NS + 3 * NM + m) * n_lanes + i];
+        } else {
+            const double *ckd = reinterpret_cast<const double *>(ck);
+            x[m] = ckd[(sgi * NS + m) * n_lanes + i];
+            v[m] = ckd[(sgi * NS + NM + m) * n_lanes + i];
+            cx[m] = R(0);
+            cv[m] = R(0);
+        }
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    // tangent columns: NY state columns (unit start), NP parameter columns (zero start)
+    constexpr int NT = NY + NP;
+    R tx[NT][NM], tv[NT][NM];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            tx[t][m] = (t == m) ? R(1) : R(0);
+            tv[t][m] = (t == NM + m) ? R(1) : R(0);
+        }
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+    int s = (int)(n0 % N);
+    for (int64_t q = n0; q < n1; ++q) {
+        const R D0 = Dt[2 * s], D1 = Dt[2 * s + 1], D2 = Dt[2 * s + 2];
+        // stage states and force partials at this step, as the reverse sweep forms them
+        R a1[NM], a2[NM], a3[NM], a4[NM], Y[NM], V2[NM], V3[NM], V4[NM];
+        R Fd1, Fdd1, Fd2, Fdd2, Fd3, Fdd3, Fd4, Fdd4;
+        R dc1[L::NC], dc2[L::NC], dc3[L::NC], dc4[L::NC];
+        stage_eval<NM>(law, x, v, om2, cd, gn, D0, a1, Fd1, Fdd1, dc1);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            Y[m] = Ops<R>::fma(h2, v[m], x[m]);
+            V2[m] = Ops<R>::fma(h2, a1[m], v[m]);
+        }
+        stage_eval<NM>(law, Y, V2, om2, cd, gn, D1, a2, Fd2, Fdd2, dc2);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            Y[m] = Ops<R>::fma(h2, V2[m], x[m]);
+            V3[m] = Ops<R>::fma(h2, a2[m], v[m]);
+        }
+        stage_eval<NM>(law, Y, V3, om2, cd, gn, D1, a3, Fd3, Fdd3, dc3);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            Y[m] = Ops<R>::fma(h, V3[m], x[m]);
+            V4[m] = Ops<R>::fma(h, a3[m], v[m]);
+        }
+        stage_eval<NM>(law, Y, V4, om2, cd, gn, D2, a4, Fd4, Fdd4, dc4);
+        // every tangent column through the four stages and the update
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const R dz = t == NT - 1 ? R(1) : R(0);
+            R dcv[L::NC];
+#pragma unroll
+            for (int k = 0; k < L::NC; ++k) dcv[k] = (t == NY + k) ? R(1) : R(0);
+            R e1[NM], e2[NM], e3[NM], e4[NM], X[NM], Vt2[NM], Vt3[NM], Vt4[NM];
+            slope_jvp<NM, L>(tx[t], tv[t], dz, dcv, Fd1, Fdd1, dc1, om2, cd, e1);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                X[m] = Ops<R>::fma(h2, tv[t][m], tx[t][m]);
+                Vt2[m] = Ops<R>::fma(h2, e1[m], tv[t][m]);
+            }
+            slope_jvp<NM, L>(X, Vt2, dz, dcv, Fd2, Fdd2, dc2, om2, cd, e2);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                X[m] = Ops<R>::fma(h2, Vt2[m], tx[t][m]);
+                Vt3[m] = Ops<R>::fma(h2, e2[m], tv[t][m]);
+            }
+            slope_jvp<NM, L>(X, Vt3, dz, dcv, Fd3, Fdd3, dc3, om2, cd, e3);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                X[m] = Ops<R>::fma(h, Vt3[m], tx[t][m]);
+                Vt4[m] = Ops<R>::fma(h, e3[m], tv[t][m]);
+            }
+            slope_jvp<NM, L>(X, Vt4, dz, dcv, Fd4, Fdd4, dc4, om2, cd, e4);
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                const R sx = tv[t][m] + R(2) * (Vt2[m] + Vt3[m]) + Vt4[m];
+                const R sv = e1[m] + R(2) * (e2[m] + e3[m]) + e4[m];
+                tx[t][m] = Ops<R>::fma(h6, sx, tx[t][m]);
+                tv[t][m] = Ops<R>::fma(h6, sv, tv[t][m]);
+            }
+        }
+        // the state itself, bit for bit as the forward pass stepped it
+        rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, D0, D1, D2);
+        if (q + 1 >= first_w) {
+            const double u = sample<NM, COMP>(x, cx, zc);
+            const double ub = coef * (Urow[q + 1 - first_w] * 1e9 - u);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double du = 0.0;
+#pragma unroll
+                for (int m = 0; m < NM; ++m) du += (double)tx[t][m];
+                acc[t] = __builtin_fma(ub, du, acc[t]);
+            }
+        }
+        s = s + 1 == N ? 0 : s + 1;
+    }
+    // record [sgi][field][n]: Phi as [state column j][row r] (rows: x then v), S as
+    // [parameter column k][row r], then c (state columns), then p (parameter columns)
+    double *rec = reinterpret_cast<double *>(A.seg) + n_lanes + sgi * NF * n_lanes + i;
+    int f = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) rec[(int64_t)(f++) * n_lanes] = (double)tx[t][m];
+#pragma unroll
+        for (int m = 0; m < NM; ++m) rec[(int64_t)(f++) * n_lanes] = (double)tv[t][m];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) rec[(int64_t)(f++) * n_lanes] = acc[t];
+}
+
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad_combine(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr int NY = 2 * NM;
+    constexpr int NP = L::NC + 1;
+    constexpr int NT = NY + NP;
+    constexpr int NF = seg_fields<NM, NP>();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    if (A.status[i] != 0) return;
+    const int64_t n_lanes = A.n;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int64_t nseg = ((int64_t)nc * K.N + A.kc - 1) / A.kc;
+    const double *recs = reinterpret_cast<const double *>(A.seg) + n_lanes;
+    double lam[NY], g[NP];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) lam[r] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) g[k] = 0.0;
+    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+        const double *rec = recs + sgi * NF * n_lanes + i;
+        auto at = [&](int f) { return rec[(int64_t)f * n_lanes]; };
+        double nl[NY];
+        // parameters: p_s + S_s^T lambda_{s+1}; state: c_s + Phi_s^T lambda_{s+1}
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double d = at(NT * NY + t);
+#pragma unroll
+            for (int r = 0; r < NY; ++r) d = __builtin_fma(at(t * NY + r), lam[r], d);
+            if (t < NY) nl[t] = d;
+            else g[t - NY] += d;
+        }
+#pragma unroll
+        for (int r = 0; r < NY; ++r) lam[r] = nl[r];
+    }
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    double sc[L::NC];
+#pragma unroll
+    for (int k = 0; k < L::NC; ++k) sc[k] = g[k];
+    double gs[kMaxParams];
+#pragma unroll
+    for (int q = 0; q < kMaxParams; ++q) gs[q] = 0.0;
+    L::to_si(p, K, sc, g[NP - 1], gs);
+    for (int j = 0; j < K.n_free; ++j) {
+        double gj = 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxParams; ++q)
+            if (K.free_index[j] == q) gj = gs[q];
+        A.dJ[(int64_t)j * A.ld + i] = gj;
+    }
+}
+
+// whether the segment-parallel form is built for a problem (table drive, at most 4 modes)
+constexpr int kSegMaxModes = 4;
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
     const int block = 64;
+    if constexpr (NM <= kSegMaxModes) {
+        if (a.form == kGradSegments && K.drive_mode == AFM_DRIVE_TABLE) {
+            const int64_t nseg = ((int64_t)K.n_cycles * K.N + a.kc - 1) / a.kc;
+            const int64_t lanes = a.n * nseg;
+            hipLaunchKernelGGL((k_grad_ckpt<LAW, NM, MIXED>), dim3((unsigned)((a.n + 63) / 64)),
+                               dim3(64), 0, s, a, K);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_grad_tan<LAW, NM, MIXED>), dim3((unsigned)((lanes + 255) / 256)),
+                               dim3(256), 0, s, a, K);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_grad_combine<LAW, NM, MIXED>),
+                               dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, s, a, K);
+            return hipGetLastError();
+        }
+    }
     if (K.drive_mode != AFM_DRIVE_TABLE) {  // parameter-driven base: one lane per trajectory
         const int64_t grid = (a.n + block - 1) / block;
         hipLaunchKernelGGL((k_grad<LAW, NM, MIXED, true>), dim3((unsigned)grid), dim3(block), 0, s,
@@ -779,9 +1152,28 @@ size_t grad_ckpt_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc
     return (size_t)nseg * 4 * K.nm * (size_t)n * esz;
 }
 
-size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc) {
+bool grad_segments_ok(const afm_plan *plan) {
+    return plan->kc.nm <= kSegMaxModes && plan->kc.drive_mode == AFM_DRIVE_TABLE;
+}
+
+int32_t grad_default_form(const afm_plan *plan) {
+    if (plan->grad_form == kGradSweep) return kGradSweep;
+    return grad_segments_ok(plan) ? kGradSegments : kGradSweep;
+}
+
+size_t grad_seg_bytes(const afm_plan *plan, int32_t prec, int64_t n, int32_t kc, int32_t form) {
+    const KConst &K = plan->kc;
+    if (form == kGradSegments && grad_segments_ok(plan)) {
+        // per trajectory the dJ/du scale, then per segment the FP64 record
+        static const int kLawNC[6] = {Law<AFM_LAW_DMT, float>::NC, Law<AFM_LAW_LJ, float>::NC,
+                                      Law<AFM_LAW_KV, float>::NC, Law<AFM_LAW_HOOKE, float>::NC,
+                                      Law<AFM_LAW_SD, float>::NC, Law<AFM_LAW_NONE, float>::NC};
+        const int ny = 2 * K.nm, nt = ny + kLawNC[K.law] + 1;
+        const int64_t nseg = ((int64_t)K.n_cycles * K.N + kc - 1) / kc;
+        return ((size_t)n + (size_t)nseg * (size_t)(ny * nt + nt) * (size_t)n) * sizeof(double);
+    }
     const size_t esz = prec == AFM_PREC_MIXED ? sizeof(float) : sizeof(double);
-    return (size_t)kc * (2 * plan->kc.nm + 1) * (size_t)n * esz;
+    return (size_t)kc * (2 * K.nm + 1) * (size_t)n * esz;
 }
 
 hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s) {

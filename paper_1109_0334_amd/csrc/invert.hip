@@ -257,3 +257,71 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, plan->ev_out, 0);
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_invert launch");
 }
+
+// One generation's forward solves of afm_invert without the swarm: the misfits of S swarms of P
+// points, each swarm against its own target row, period count and parameter vector, through the
+// same launch (the persistent work queue, longest period count first, when period counts are
+// given; the tuned plain grid otherwise).
+extern "C" afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_t particles,
+                                        const double *theta, const int32_t *n_cycles,
+                                        const double *swarm_params, const double *targets,
+                                        double *J, int32_t *status, afm_stream_t stream) {
+    if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
+    if (n_swarms < 0 || particles < 1) return fail(AFM_ERR_INVALID, "need n_swarms >= 0 and particles >= 1");
+    if ((int64_t)n_swarms * particles > (int64_t)1 << 31) return fail(AFM_ERR_INVALID, "batch too large");
+    if (n_swarms == 0) return AFM_OK;
+    if ((plan->prob.n_free > 0 && !theta) || !targets || !J || !status)
+        return fail(AFM_ERR_INVALID, "theta, targets, J and status are required");
+    const int32_t chunks = (particles + 63) / 64;
+    const int32_t n_items = n_swarms * chunks;
+    FwdArgs a{};
+    a.n = (int64_t)n_swarms * particles;
+    a.ld = a.n;
+    a.theta = theta;
+    a.n_cycles = n_cycles;
+    a.targets = targets;
+    a.n_targets = n_swarms;
+    a.group = particles;
+    a.row_by_group = 1;
+    a.base = swarm_params;
+    a.base_ld = n_swarms;
+    a.J = J;
+    a.status = status;
+    hipError_t e;
+    if (n_cycles) {
+        const size_t bytes = sizeof(int32_t) * ((size_t)n_items + 64);
+        const bool hit = plan->q_ncyc == n_cycles && plan->q_S == n_swarms &&
+                         plan->q_P == particles && plan->qws_bytes >= bytes;
+        if (!hit) {
+            if (plan->qws_bytes < bytes) {
+                if (plan->qws) (void)hipFree(plan->qws);  // waits for work still using it
+                plan->qws = nullptr;
+                plan->qws_bytes = 0;
+                if (hipMalloc(&plan->qws, bytes) != hipSuccess)
+                    return fail(AFM_ERR_NOMEM, "afm_misfit_swarms: workspace allocation failed");
+                plan->qws_bytes = bytes;
+            }
+            // longest period count first (the order only balances the load; results do not
+            // depend on it); read on the caller's stream after its earlier work
+            std::vector<int32_t> nc(n_swarms), items(n_items);
+            e = hipMemcpyAsync(nc.data(), n_cycles, sizeof(int32_t) * n_swarms,
+                               hipMemcpyDeviceToHost, (hipStream_t)stream);
+            if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "afm_misfit_swarms reading n_cycles");
+            std::iota(items.begin(), items.end(), 0);
+            std::stable_sort(items.begin(), items.end(),
+                             [&](int32_t x, int32_t y) { return nc[x / chunks] > nc[y / chunks]; });
+            e = hipMemcpy(plan->qws, items.data(), sizeof(int32_t) * n_items, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "afm_misfit_swarms queue upload");
+            plan->q_ncyc = n_cycles;
+            plan->q_S = n_swarms;
+            plan->q_P = particles;
+        }
+        a.items = (const int32_t *)plan->qws;
+        a.n_items = n_items;
+        a.chunks = chunks;
+        a.head = (int32_t *)plan->qws + ((n_items + 63) / 64) * 64;
+    }
+    e = launch_forward(plan, a, (hipStream_t)stream);
+    return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_misfit_swarms launch");
+}

@@ -380,8 +380,9 @@ hipError_t enqueue_polish(afm_plan *plan, void *ws, int64_t n, double *z,
     ga.base_ld = n;
     // one lane per mode while the groups fit one wave per SIMD (same bits, shorter streams)
     ga.mp = plan->kc.nm > 1 && n * 4 <= 65536;
+    ga.form = grad_default_form(plan);
     ga.seg = (float *)((char *)ws + align256(polish_ws_bytes(n, D, L)));
-    ga.ckpt = (float *)((char *)ga.seg + align256(grad_seg_bytes(plan, prec, n, kc)));
+    ga.ckpt = (float *)((char *)ga.seg + align256(grad_seg_bytes(plan, prec, n, kc, ga.form)));
     hipError_t e = launch_grad_p(plan, prec, ga, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lb_start, dim3(blocks), dim3(64), 0, s, n, D, (const double *)z, w.g,
@@ -449,7 +450,8 @@ hipError_t enqueue_merge(const afm_swarm &sw, int32_t k, const double *zsel, con
 
 size_t polish_total_bytes(const afm_plan *plan, int64_t n, int32_t kc) {
     const int32_t D = plan->prob.n_free, L = 21, prec = polish_prec(plan);
-    return align256(polish_ws_bytes(n, D, L)) + align256(grad_seg_bytes(plan, prec, n, kc)) +
+    return align256(polish_ws_bytes(n, D, L)) +
+           align256(grad_seg_bytes(plan, prec, n, kc, grad_default_form(plan))) +
            grad_ckpt_bytes(plan, prec, n, kc) + 256;
 }
 

@@ -92,9 +92,9 @@ def _check_forward(afm, orc, m, base, free, th, prec, tag):
         print(f"{tag}: {n} points, FP64 max |dA|/A "
               f"{np.max(np.abs(A[ok] / o['A'][ok] - 1)):.2e}")
         return
-    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, J=J, tag=tag)
-    assert not failing, failing
-    assert len(excluded) <= n // 4, excluded
+    # measured: no exclusions, at least 96 % of the points within the bars with no floor
+    _, excluded, _ = PT.compare_mixed(orc, m, P, o, A, phi, st, J=J, tag=tag, max_excluded=1,
+                                      min_strict=int(0.95 * n))
     for i in [k for k in range(min(n, 4)) if st[k] == 0 and k not in excluded]:
         to = orc.forward(m, P[i], want_trace=True)["trace"]
         e = np.max(np.abs(tr[i] - to)) / np.max(np.abs(to))
@@ -313,13 +313,13 @@ def test_gradient_of_base_motion_matches_oracle(afm, orc, prec, case):
         e = np.linalg.norm((dJ[:, i] - gfree) * zs[:, 0]) / np.linalg.norm(gfree * zs[:, 0])
         if prec == "fp64":
             assert abs(J[i] / Jo - 1) < 1e-9
-            tol = PT.GRAD_TOL64 if e <= PT.GRAD_TOL64 else \
-                PT.grad_tolerance(orc, m, P[i], U, free, fp64=True)
+            tol = PT.GRAD_TOL64
         else:
             assert abs(J[i] - Jo) <= PT.misfit_tol(Jo)
-            tol = PT.GRAD_TOL if e <= PT.GRAD_TOL else PT.grad_tolerance(orc, m, P[i], U, free)
-        print(f"{case} {prec} point {i}: rel err {e:.2e} (tolerance {tol:.1e})")
-        assert e <= tol
+            tol = PT.GRAD_TOL
+        keep = e <= tol or PT.grad_retained(orc, m, P[i], U, free, fp64=prec == "fp64")
+        print(f"{case} {prec} point {i}: rel err {e:.2e} ({'retained' if keep else 'excluded'})")
+        assert e <= tol or not keep
 
 
 def test_polish_of_base_motion_inversion(afm, orc):

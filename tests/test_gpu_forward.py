@@ -56,9 +56,8 @@ def test_forward_mixed_c2(afm, orc):
     A, phi, st = _np(plan.forward_batch(th))
     P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
     o = PT.oracle_batch(orc, c["model"], P)
-    failing, excluded = PT.compare_mixed(orc, c["model"], P, o, A, phi, st, tag="mixed C2")
-    assert not failing, failing
-    assert len(excluded) <= 3
+    PT.compare_mixed(orc, c["model"], P, o, A, phi, st, tag="mixed C2", max_excluded=1,
+                     min_strict=128)
 
 
 def test_misfit_mixed_c2_noisy_target(afm, orc):
@@ -75,10 +74,8 @@ def test_misfit_mixed_c2_noisy_target(afm, orc):
     A, phi, _ = _np(plan.forward_batch(th))
     P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
     o = PT.oracle_batch(orc, m, P, target=U)
-    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st.cpu().numpy(),
-                                         J=J.cpu().numpy(), tag="misfit C2")
-    assert not failing, failing
-    assert len(excluded) <= 2
+    PT.compare_mixed(orc, m, P, o, A, phi, st.cpu().numpy(), J=J.cpu().numpy(), tag="misfit C2",
+                     max_excluded=1, min_strict=68)
 
 
 def test_trace_and_lockin_fp64(afm, orc):
@@ -124,11 +121,13 @@ def _law_case(law):
     return m, base, free, th
 
 
-# Allowed excluded (ill-conditioned) trajectories per case.  The LJ workload at 256 steps per
-# period resolves its steep repulsive wall with few steps: its discrete orbit is not converged in
-# the step (A moves by ~1e-4 between 256 and 512 steps) and a sizeable part of the box is
-# ill-conditioned; at 512 steps it behaves like the other laws.
-_EXCLUDE = {"lj": 12, "lj512": 1, "kv3": 1, "dmt3": 1, "hooke": 1, "sd": 1, "none": 0}
+# Allowed excluded (ill-conditioned) trajectories and required strict-bar counts per case (the
+# measured counts with a margin of one or two).  The LJ workload at 256 steps per period resolves
+# its steep repulsive wall with few steps: 3 of its 24 points are excluded (two whose steady orbit
+# moves with the data at the 1e-7 level, one whose crash through the wall flips with its initial
+# state); at 512 steps it behaves like the other laws.
+_EXCLUDE = {"lj": 4, "lj512": 1, "kv3": 1, "dmt3": 1, "hooke": 1, "sd": 1, "none": 0}
+_MIN_STRICT = {"lj": 19, "lj512": 23, "kv3": 10, "dmt3": 10, "hooke": 19, "sd": 19, "none": 19}
 
 
 @pytest.mark.parametrize("law", ["lj", "lj512", "kv3", "hooke", "sd", "none", "dmt3"])
@@ -138,10 +137,8 @@ def test_forward_mixed_other_laws(afm, orc, law):
     A, phi, st = _np(plan.forward_batch(th))
     P = PT.full_from_free(base, free, th)
     o = PT.oracle_batch(orc, m, P)
-    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, tag=law)
-    assert not failing, [(i, A[i], o["A"][i], phi[i], o["phi"][i], st[i], o["status"][i])
-                         for i in failing]
-    assert len(excluded) <= _EXCLUDE[law]
+    PT.compare_mixed(orc, m, P, o, A, phi, st, tag=law, max_excluded=_EXCLUDE[law],
+                     min_strict=_MIN_STRICT[law])
 
 
 @pytest.mark.parametrize("law", ["lj", "kv3"])
@@ -214,9 +211,8 @@ def test_per_trajectory_cycles(afm, orc):
     A, phi, st = _np(plan.forward_batch(th, n_cycles=cyc))
     P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
     o = PT.oracle_batch(orc, c["model"], P, n_cycles=cyc)
-    failing, excluded = PT.compare_mixed(orc, c["model"], P, o, A, phi, st, tag="uneven",
-                                         n_cycles=cyc)
-    assert not failing and len(excluded) <= 2
+    PT.compare_mixed(orc, c["model"], P, o, A, phi, st, tag="uneven", n_cycles=cyc,
+                     max_excluded=3, min_strict=35)
 
 
 def test_full_size_c2_sampled(afm, orc):
@@ -250,8 +246,8 @@ def test_saturating_batch_sampled(afm, orc):
     idx = np.random.default_rng(16).choice(n, 16, replace=False)
     P = PT.full_from_free(W.full_params(c), W.free_index(c), th[:, idx])
     o = PT.oracle_batch(orc, m, P)
-    failing, excluded = PT.compare_mixed(orc, m, P, o, A[idx], phi[idx], st[idx], tag="saturating")
-    assert not failing and len(excluded) <= 1
+    PT.compare_mixed(orc, m, P, o, A[idx], phi[idx], st[idx], tag="saturating", max_excluded=1,
+                     min_strict=15)
 
 
 @pytest.mark.parametrize("N", [4, 5, 203, 4096])
@@ -284,8 +280,7 @@ def test_steps_per_period_edges_mixed(afm, orc, N):
     A, phi, st = _np(plan.forward_batch(th))
     P = PT.full_from_free(W.full_params(c), W.free_index(c), th)
     o = PT.oracle_batch(orc, m, P)
-    failing, excluded = PT.compare_mixed(orc, m, P, o, A, phi, st, tag=f"N={N}")
-    assert not failing and len(excluded) <= 2
+    PT.compare_mixed(orc, m, P, o, A, phi, st, tag=f"N={N}", max_excluded=1, min_strict=38)
 
 
 @pytest.mark.parametrize("precision,n,nc", [("mixed", 1000, 60), ("fp64", 333, 40),
@@ -368,6 +363,52 @@ def test_mode_parallel_bit_identical(afm, orc, nm, law):
     idx = rng.choice(n, 6, replace=False)
     P = PT.full_from_free(base, free, th[:, idx])
     o = PT.oracle_batch(orc, m, P)
-    failing, excluded = PT.compare_mixed(orc, m, P, o, ref["amp"][idx], ref["phase"][idx],
-                                         ref["status"][idx], tag=f"{nm}-mode {law}")
-    assert not failing and len(excluded) <= 1
+    PT.compare_mixed(orc, m, P, o, ref["amp"][idx], ref["phase"][idx], ref["status"][idx],
+                     tag=f"{nm}-mode {law}", max_excluded=1, min_strict=5)
+
+
+def test_misfit_swarms_work_queue(afm, orc):
+    """afm_misfit_swarms (one generation's forward of afm_invert) on 37 swarms of 100 points with
+    uneven period counts and per-swarm separations: the persistent work queue gives the bits of
+    afm_misfit with per-point target rows, period counts and parameters (the plain one-lane
+    launch, same force form below 65536 trajectories), and sampled points match the oracle; a
+    second call reuses the queue order."""
+    import torch
+
+    c = W.config("c2")
+    m = dict(c["model"], n_cycles=300)
+    S, P = 37, 100
+    base, free = W.full_params(c), W.free_index(c)
+    rng = np.random.default_rng(70)
+    cyc = torch.tensor(rng.integers(20, 300, S).astype(np.int32), device="cuda")
+    sp = np.zeros((12, S))
+    sp[:len(base)] = np.asarray(base)[:, None]
+    sp[0] = rng.uniform(13e-9, 16e-9, S)
+    U = np.stack([orc.forward(dict(m, n_cycles=int(n)), sp[:len(base), s], want_trace=True)["trace"]
+                  for s, n in zip(range(S), cyc.cpu().numpy())])
+    th = _theta(c, S * P, 71)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    J1, st1 = (x.cpu().numpy() for x in plan.misfit_swarms(th, U, P, n_cycles=cyc, swarm_params=sp))
+    J2, st2 = (x.cpu().numpy() for x in plan.misfit_swarms(th, U, P, n_cycles=cyc, swarm_params=sp))
+    assert np.array_equal(J1.view(np.uint64), J2.view(np.uint64)) and np.array_equal(st1, st2)
+    tid = np.repeat(np.arange(S, dtype=np.int32), P)
+    ncl = np.repeat(cyc.cpu().numpy(), P)
+    # afm_misfit with the same per-point inputs: per-point parameters go in through theta
+    # (z_c is not free here), so compare against a plan whose free set includes z_c
+    free_z = [(0, 1e-9, 30e-9, 0)] + free
+    plan_z = afm.Plan(m, base, free_z, precision="mixed")
+    thz = np.vstack([np.repeat(sp[0], P)[None, :], th])
+    Jm, stm = (x.cpu().numpy() for x in plan_z.misfit(thz, U, target_id=tid, n_cycles=ncl))
+    assert np.array_equal(stm, st1)
+    assert np.array_equal(Jm.view(np.uint64), J1.view(np.uint64))
+    idx = rng.choice(S * P, 12, replace=False)
+    for i in idx:
+        s = i // P
+        p = sp[:len(base), s].copy()
+        for j, f in enumerate(free):
+            p[f[0]] = th[j, i]
+        o = orc.forward(dict(m, n_cycles=int(ncl[i])), p, U[s])
+        assert (st1[i] != 0) == (o["status"] != 0)
+        if st1[i] == 0:
+            assert abs(J1[i] - o["J"]) <= PT.misfit_tol(o["J"]) or \
+                not PT.well_conditioned(orc, dict(m, n_cycles=int(ncl[i])), p)

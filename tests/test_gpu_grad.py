@@ -1,10 +1,13 @@
 """GPU discrete adjoint (afm_grad_batch) against the oracle's adjoint and finite differences.
 
 Errors are norm-wise in normalised coordinates, |g - g_ref|_2 / |g_ref|_2 per parameter point
-with g_z = dJ/dz = dJ/dtheta * dtheta/dz over the search box.  A point passes when its error is
-below its tolerance: 1e-3 (mixed) or 1e-6 (FP64), widened where the oracle's own gradient
-changes by more than a third of that under FP32-sized (resp. FP64-sized) changes of the data
-(see parity.py).  The tests print how many points needed the widened tolerance."""
+with g_z = dJ/dz = dJ/dtheta * dtheta/dz over the search box.  Retained points (the oracle's own
+gradient moves by at most a third of the bar when its data change by 1e-7 relative, mixed, or
+1e-10, FP64; see parity.py) are held to 1e-3 (mixed) or 1e-6 (FP64); the others are excluded,
+counted and bounded per case.  Over the 1000-period Lennard-Jones-type horizon most of the box is
+excluded: there the misfit varies on scales far below a 1e-4 relative parameter step (the oracle
+adjoint and its own central differences disagree by up to 3x), so no gradient is determined to
+1e-3 by FP32-resolved data."""
 import numpy as np
 import pytest
 
@@ -35,13 +38,7 @@ def _zscale(free, theta):
 
 
 def _oracle_grads(orc, m, P, free, U):
-    g = np.empty((len(free), P.shape[0]))
-    J = np.empty(P.shape[0])
-    st = np.empty(P.shape[0], np.int32)
-    for i in range(P.shape[0]):
-        st[i], J[i], gf = orc.misfit_grad(m, P[i], U)
-        g[:, i] = [gf[f[0]] for f in free]
-    return J, g, st
+    return PT.oracle_grads_many(orc, m, P, free, U)
 
 
 def _case(name):
@@ -52,7 +49,7 @@ def _case(name):
         return c, m, W.full_params(c), W.free_index(c), th
     if name == "lj-c4":
         c = W.config("c4")
-        return c, c["model"], W.full_params(c), W.free_index(c), W.draw_free(c, 20, 22).T.copy()
+        return c, c["model"], W.full_params(c), W.free_index(c), W.draw_free(c, 96, 22).T.copy()
     if name == "kv3-c5":
         c = W.config("c5")
         m = dict(c["model"], n_cycles=120)
@@ -88,42 +85,78 @@ def test_grad_fp64_matches_oracle_adjoint(afm, orc):
     assert err.max() < 1e-7
 
 
+# Retained points required per case (the measured count less a margin: the retained set is
+# computed by the oracle alone, so it changes only with the oracle or the inputs), and the points
+# within 1e-3 among all finite ones, whatever their conditioning (measured less a margin).  Most
+# of each box is excluded at these horizons (see parity.py).
+_GRAD_MIN_RETAINED = {"dmt-c2": 14, "lj-c4": 15, "kv3-c5": 6}
+_GRAD_MIN_WITHIN = {"dmt-c2": 17, "lj-c4": 9, "kv3-c5": 4}
+
+_ORC_CACHE = {}
+_GPU_CACHE = {}
+
+
+def _oracle_case(orc, name):
+    """Inputs, oracle gradients and the retained mask of a case (cached across tests)."""
+    if name not in _ORC_CACHE:
+        c, m, base, free, th = _case(name)
+        U = _target(orc, c, m, base)
+        P = PT.full_from_free(base, free, th)
+        Jo, go, sto = _oracle_grads(orc, m, P, free, U)
+        keep = PT.grad_retained_many(orc, m, P, U, free)
+        _ORC_CACHE[name] = dict(c=c, m=m, base=base, free=free, th=th, U=U, P=P, Jo=Jo, go=go,
+                                sto=sto, keep=keep)
+    return _ORC_CACHE[name]
+
+
+def _gpu_case(afm, orc, name, form, prec="mixed"):
+    key = (name, form, prec)
+    if key not in _GPU_CACHE:
+        d = _oracle_case(orc, name)
+        plan = afm.Plan(d["m"], d["base"], d["free"], precision=prec)
+        plan.set_grad_form(form)
+        J, dJ, st = (x.cpu().numpy() for x in plan.grad_batch(d["th"], d["U"][None, :]))
+        Jm, _ = plan.misfit(d["th"], d["U"][None, :])
+        assert np.array_equal(J, Jm.cpu().numpy())  # same forward arithmetic as afm_misfit
+        plan.close()
+        _GPU_CACHE[key] = (J, dJ, st)
+    return _GPU_CACHE[key]
+
+
+@pytest.mark.parametrize("form", ["sweep", "segments"])
 @pytest.mark.parametrize("name", ["dmt-c2", "lj-c4", "kv3-c5"])
-def test_grad_mixed_matches_oracle_adjoint(afm, orc, name):
-    c, m, base, free, th = _case(name)
-    U = _target(orc, c, m, base)
-    plan = afm.Plan(m, base, free, precision="mixed")
-    J, dJ, st = plan.grad_batch(th, U[None, :])
-    J, dJ, st = J.cpu().numpy(), dJ.cpu().numpy(), st.cpu().numpy()
-    Jm, _ = plan.misfit(th, U[None, :])
-    assert np.array_equal(J, Jm.cpu().numpy())  # same forward arithmetic as afm_misfit
-    P = PT.full_from_free(base, free, th)
-    Jo, go, sto = _oracle_grads(orc, m, P, free, U)
-    zs = _zscale(free, th)
+def test_grad_mixed_matches_oracle_adjoint(afm, orc, name, form):
+    d = _oracle_case(orc, name)
+    J, dJ, st = _gpu_case(afm, orc, name, form)
+    sto, keep, go = d["sto"], d["keep"], d["go"]
+    zs = _zscale(d["free"], d["th"])
+    # failure status agrees wherever the oracle's verdict is decided at the solver's resolution
+    for i in np.flatnonzero((st != 0) != (sto != 0)):
+        assert not PT.fate_conditioned(orc, d["m"], d["P"][i]), (name, int(i), st[i], sto[i])
     ok = (st == 0) & (sto == 0)
-    assert np.array_equal(st != 0, sto != 0) or all(
-        PT.grad_tolerance(orc, m, P[i], U, free) > PT.GRAD_TOL for i in np.flatnonzero(st != sto))
-    err = np.full(len(J), np.nan)
+    err = np.full(len(st), np.nan)
     err[ok] = np.linalg.norm((dJ[:, ok] - go[:, ok]) * zs[:, ok], axis=0) / \
         np.linalg.norm(go[:, ok] * zs[:, ok], axis=0)
-    widened, failing = 0, []
-    for i in np.flatnonzero(ok & (err > PT.GRAD_TOL)):
-        tol = PT.grad_tolerance(orc, m, P[i], U, free)
-        widened += 1
-        if err[i] > tol:
-            failing.append((int(i), err[i], tol))
-    print(f"{name}: n {len(J)}, median rel err {np.nanmedian(err):.2e}, max {np.nanmax(err):.2e}, "
-          f"within 1e-3 {int(np.sum(err[ok] <= PT.GRAD_TOL))}, needed a widened tolerance "
-          f"{widened}, failing {len(failing)}")
-    assert not failing, failing
+    ret = keep & ok
+    n_within = int(np.sum(err[ok] <= PT.GRAD_TOL))
+    print(f"{name} {form}: n {len(st)}, retained {int(ret.sum())} (max rel err "
+          f"{np.nanmax(err[ret]):.2e}, median {np.nanmedian(err[ret]):.1e}, within 1e-3 "
+          f"{int(np.sum(err[ret] <= PT.GRAD_TOL))}), excluded {int(np.sum(ok & ~keep))} (median "
+          f"rel err there {np.nanmedian(err[ok & ~keep]):.1e}); all finite points within 1e-3: "
+          f"{n_within} of {int(ok.sum())}")
+    assert int(ret.sum()) >= _GRAD_MIN_RETAINED[name]
+    assert np.max(err[ret]) <= PT.GRAD_TOL_MIXED, [(int(i), err[i]) for i in np.flatnonzero(ret)
+                                                    if err[i] > PT.GRAD_TOL_MIXED]
+    assert np.median(err[ret]) <= PT.GRAD_TOL
+    assert n_within >= _GRAD_MIN_WITHIN[name]
 
 
 def test_grad_mixed_vs_central_differences(afm, orc):
-    """Central differences of the FP64 oracle misfit agree with the GPU adjoint to 1e-3
-    (norm-wise, normalised coordinates) on well-conditioned points (a 100-period horizon, where
-    most of the box is well conditioned).  The differences are Richardson-extrapolated from
-    h = 1e-4 and 5e-5 relative: a plain central difference at 1e-4 carries an O(h^2) truncation
-    error that alone reaches 1e-3 where the misfit is strongly curved."""
+    """Central differences of the FP64 oracle misfit agree with the mixed GPU adjoint to 1e-3
+    (norm-wise, normalised coordinates) on retained points of a 100-period horizon.  The
+    differences are Richardson-extrapolated from h = 1e-4 and 5e-5 relative: a plain central
+    difference at 1e-4 carries an O(h^2) truncation error that alone reaches 1e-3 where the
+    misfit is strongly curved."""
     c, m, base, free, th = _case("dmt-c2")
     m = dict(m, n_cycles=100)
     U = _target(orc, c, m, base)
@@ -132,11 +165,12 @@ def test_grad_mixed_vs_central_differences(afm, orc):
     dJ, st = dJ.cpu().numpy(), st.cpu().numpy()
     P = PT.full_from_free(base, free, th)
     zs = _zscale(free, th)
+    keep = PT.grad_retained_many(orc, m, P, U, free)
     checked = 0
     for i in range(th.shape[1]):
         if checked == 6:
             break
-        if st[i] != 0 or PT.grad_tolerance(orc, m, P[i], U, free) > PT.GRAD_TOL:
+        if st[i] != 0 or not keep[i]:
             continue
         fd = np.empty(len(free))
         for j, f in enumerate(free):
@@ -150,20 +184,62 @@ def test_grad_mixed_vs_central_differences(afm, orc):
             fd[j] = (4.0 * cd[1] - cd[0]) / 3.0
         e = np.linalg.norm((dJ[:, i] - fd) * zs[:, i]) / np.linalg.norm(fd * zs[:, i])
         print(f"point {i}: adjoint vs central differences {e:.2e}")
-        assert e < 1e-3, (i, dJ[:, i], fd)
+        assert e < PT.GRAD_TOL, (i, dJ[:, i], fd)
         checked += 1
     assert checked >= 4
 
 
+def test_grad_vs_central_differences_c4(afm, orc):
+    """The 1000-period LJ-type workload at full length (1000 x 256 steps), 8 retained points:
+    plain central differences of the FP64 oracle misfit (h = 1e-4 relative per parameter) agree
+    with the oracle's adjoint and with the GPU's FP64 adjoint to 1e-3, and with the GPU's mixed
+    adjoint (both forms) to the mixed bar."""
+    d = _oracle_case(orc, "lj-c4")
+    m, free, P, U = d["m"], d["free"], d["P"], d["U"]
+    zs = _zscale(free, d["th"])
+    mixed = {f: _gpu_case(afm, orc, "lj-c4", f) for f in ("sweep", "segments")}
+    pts = [int(i) for i in np.flatnonzero(d["keep"] & (mixed["sweep"][2] == 0))][:8]
+    assert len(pts) == 8
+    plan64 = afm.Plan(m, d["base"], free, precision="fp64")
+    _, dJ64, st64 = (x.cpu().numpy() for x in plan64.grad_batch(d["th"][:, pts], U[None, :]))
+    assert np.all(st64 == 0)
+
+    def cd(i):
+        g = np.empty(len(free))
+        for j, f in enumerate(free):
+            hj = 1e-4 * abs(P[i, f[0]])
+            pp, pm = P[i].copy(), P[i].copy()
+            pp[f[0]] += hj
+            pm[f[0]] -= hj
+            g[j] = (orc.forward(m, pp, U)["J"] - orc.forward(m, pm, U)["J"]) / (2 * hj)
+        return g
+
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(8) as ex:
+        fds = list(ex.map(cd, pts))
+    for k, (i, fd) in enumerate(zip(pts, fds)):
+        den = np.linalg.norm(fd * zs[:, i])
+        e = {"oracle": d["go"][:, i], "fp64": dJ64[:, k], "sweep": mixed["sweep"][1][:, i],
+             "segments": mixed["segments"][1][:, i]}
+        e = {kk: np.linalg.norm((v - fd) * zs[:, i]) / den for kk, v in e.items()}
+        print(f"c4 point {i}: vs central differences: oracle adjoint {e['oracle']:.2e}, GPU FP64 "
+              f"{e['fp64']:.2e}, GPU mixed sweep {e['sweep']:.2e}, segments {e['segments']:.2e}")
+        assert e["oracle"] < PT.GRAD_TOL and e["fp64"] < PT.GRAD_TOL, (i, e)
+        assert e["sweep"] < PT.GRAD_TOL_MIXED and e["segments"] < PT.GRAD_TOL_MIXED, (i, e)
+
+
 def test_ckpt_stride_invariance(afm, orc):
-    """The recomputation is bit-identical and the reverse walk visits the steps in the same
-    order for every stride, so J and dJ are independent of the checkpoint stride bit for bit."""
+    """Reverse-sweep form: the recomputation is bit-identical and the reverse walk visits the
+    steps in the same order for every stride, so J and dJ are independent of the checkpoint
+    stride bit for bit."""
     c = W.config("c2")
     m = dict(c["model"], n_cycles=50)
     base, free = W.full_params(c), W.free_index(c)
     th = W.draw_free(c, 70, 24).T.copy()
     U = _target(orc, c, m, base)
     plan = afm.Plan(m, base, free, precision="mixed")
+    plan.set_grad_form("sweep")
     ref = None
     for kc in (1, 7, 64, 256, 50 * 256, 0):
         J, dJ, st = plan.grad_batch(th, U[None, :], ckpt_stride=kc)
@@ -173,6 +249,45 @@ def test_ckpt_stride_invariance(afm, orc):
             continue
         assert np.array_equal(J, ref[0]), kc
         assert np.array_equal(dJ, ref[1]), (kc, np.max(np.abs(dJ / ref[1] - 1)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_segment_form_matches_sweep_and_oracle(afm, orc, prec):
+    """Segment-parallel form (tangent columns per checkpoint segment, combined by the backward
+    recursion) at strides from 1 step to the whole trajectory, ragged segments included: J equals
+    the sweep's bit for bit, and dJ agrees with the sweep and with the oracle's exact adjoint --
+    FP64 to 1e-9 on every point, mixed to 1e-3 on retained points -- with the same statuses."""
+    c = W.config("c2")
+    m = dict(c["model"], n_cycles=30)
+    base, free = W.full_params(c), W.free_index(c)
+    th = W.draw_free(c, 67, 26).T.copy()
+    th[1, 3] = 1e15  # a trajectory that fails
+    U = _target(orc, c, m, base)
+    plan = afm.Plan(m, base, free, precision=prec)
+    plan.set_grad_form("sweep")
+    Js, dJs, sts = (x.cpu().numpy() for x in plan.grad_batch(th, U[None, :], ckpt_stride=64))
+    plan.set_grad_form("segments")
+    P = PT.full_from_free(base, free, th)
+    Jo, go, sto = _oracle_grads(orc, m, P, free, U)
+    zs = _zscale(free, th)
+    ok = sts == 0
+    keep = PT.grad_retained_many(orc, m, P, U, free, fp64=prec == "fp64") & ok
+    for kc in (1, 7, 64, 256, 30 * 256, 0):
+        J, dJ, st = (x.cpu().numpy() for x in plan.grad_batch(th, U[None, :], ckpt_stride=kc))
+        assert np.array_equal(st, sts), kc
+        assert np.array_equal(J.view(np.uint64)[ok], Js.view(np.uint64)[ok]), kc
+        assert np.all(np.isnan(dJ[:, ~ok])), kc
+        e_s = np.linalg.norm((dJ[:, ok] - dJs[:, ok]) * zs[:, ok], axis=0) / \
+            np.linalg.norm(dJs[:, ok] * zs[:, ok], axis=0)
+        e_o = np.linalg.norm((dJ - go) * zs, axis=0) / np.linalg.norm(go * zs, axis=0)
+        print(f"{prec} stride {kc}: segments vs sweep max {e_s.max():.2e}, vs oracle on "
+              f"{int(keep.sum())} retained max {e_o[keep].max():.2e}")
+        if prec == "fp64":
+            assert e_s.max() <= 1e-9 and e_o[ok].max() <= 1e-9, kc
+        else:
+            assert e_o[keep].max() <= PT.GRAD_TOL_MIXED and np.median(e_o[keep]) <= PT.GRAD_TOL, kc
+            assert np.median(e_s) <= 1e-4, kc
+    assert not ok[3] and int(keep.sum()) >= (40 if prec == "fp64" else 10)
 
 
 def test_autograd_function(afm, orc):
@@ -194,8 +309,9 @@ def test_autograd_function(afm, orc):
 
 
 def test_grad_fp64_other_laws(afm, orc):
-    """FP64 adjoint for LJ (full C4 length) and the 3-mode Kelvin-Voigt beam: no exclusions."""
-    for name in ("lj-c4", "kv3-c5"):
+    """FP64 adjoint for LJ (full C4 length) and the 3-mode Kelvin-Voigt beam: 1e-6 on points
+    whose oracle gradient is determined to that bar by FP64-resolved data."""
+    for name, cap in (("lj-c4", 6), ("kv3-c5", 2)):
         c, m, base, free, th = _case(name)
         th = th[:, :6]
         U = _target(orc, c, m, base)
@@ -207,12 +323,15 @@ def test_grad_fp64_other_laws(afm, orc):
         assert np.array_equal(st, sto)
         ok = st == 0
         zs = _zscale(free, th)
-        err = np.linalg.norm((dJ[:, ok] - go[:, ok]) * zs[:, ok], axis=0) / \
+        err = np.full(len(st), np.nan)
+        err[ok] = np.linalg.norm((dJ[:, ok] - go[:, ok]) * zs[:, ok], axis=0) / \
             np.linalg.norm(go[:, ok] * zs[:, ok], axis=0)
-        print(f"fp64 {name}: median rel err {np.median(err):.2e}, max {err.max():.2e}")
-        for k, i in enumerate(np.flatnonzero(ok)):
-            if err[k] > PT.GRAD_TOL64:
-                assert err[k] <= PT.grad_tolerance(orc, m, P[i], U, free, fp64=True), (name, i)
+        keep = PT.grad_retained_many(orc, m, P, U, free, fp64=True) & ok
+        print(f"fp64 {name}: retained {int(keep.sum())} of {len(st)} (max rel err "
+              f"{np.nanmax(err[keep]) if keep.any() else np.nan:.2e}), all points median "
+              f"{np.nanmedian(err):.2e}, max {np.nanmax(err):.2e}")
+        assert np.all(err[keep] <= PT.GRAD_TOL64), (name, err)
+        assert int(np.sum(ok & ~keep)) <= cap, name
 
 
 @pytest.mark.parametrize("nm", [2, 3, 4, 5, 6, 7, 8])
@@ -235,6 +354,7 @@ def test_grad_mode_parallel_bit_identical(afm, orc, nm):
                    rng.uniform(f[1], f[2], n) for f in free])
     U = _target(orc, c, m, base)
     plan = afm.Plan(m, base, free, precision="mixed")
+    plan.set_grad_form("sweep")
     ref = None
     for kc in (16, 64, 256):
         r = [x.cpu().numpy() for x in plan.grad_batch(th, U[None, :], ckpt_stride=kc)]
@@ -276,6 +396,6 @@ def test_grad_eight_modes_matches_oracle_adjoint(afm, orc):
             continue
         assert abs(J[i] - Jo[i]) <= PT.misfit_tol(Jo[i]) or not PT.well_conditioned(orc, m, P[i])
         e = np.linalg.norm((dJ[:, i] - go[:, i]) * zs[:, i]) / np.linalg.norm(go[:, i] * zs[:, i])
-        tol = PT.GRAD_TOL if e <= PT.GRAD_TOL else PT.grad_tolerance(orc, m, P[i], U, free)
-        print(f"8-mode point {i}: rel err {e:.2e} (tolerance {tol:.1e})")
-        assert e <= tol
+        keep = PT.grad_retained(orc, m, P[i], U, free)
+        print(f"8-mode point {i}: rel err {e:.2e} ({'retained' if keep else 'excluded'})")
+        assert e <= PT.GRAD_TOL or not keep
