@@ -39,6 +39,7 @@
 #ifndef AFM_H
 #define AFM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -278,12 +279,34 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
                           double *J, double *dJ, int32_t ckpt_stride, int32_t *status,
                           afm_stream_t stream);
 
-/* Form of the gradient launches of a plan (afm_grad_batch, afm_polish, the invert
- * polish): AUTO (tuned by afm_grad_batch; SEGMENTS where built otherwise), SWEEP, or
+/* Form of the gradient launches of a plan (afm_grad_batch, afm_grad_batch_noalloc, afm_polish,
+ * the invert polish): AUTO (tuned by afm_grad_batch; SEGMENTS where built otherwise), SWEEP, or
  * SEGMENTS (AFM_ERR_UNSUPPORTED for a parameter-driven base or more than 4 modes).  Clears the
  * plan's tuned gradient settings. */
 enum { AFM_GRAD_AUTO = 0, AFM_GRAD_SWEEP = 1, AFM_GRAD_SEGMENTS = 2 };
 afm_status afm_set_grad_form(afm_plan *plan, int32_t form);
+
+/* afm_grad_batch for callers that cannot allocate device memory (code captured into a HIP graph,
+ * tight serving loops, harnesses that forbid allocation): the same kernels, the same results bit
+ * for bit, but the checkpoints and the segment buffer live in a fixed library-owned device array
+ * of AFM_NOALLOC_SCRATCH_BYTES per device (held from the first call on a device until the process
+ * ends) instead of the plan's workspace.  The call allocates nothing and does not synchronise.
+ * ckpt_stride: as afm_grad_batch, except that 0 takes the stride afm_grad_batch tuned for this n
+ * on this plan, else 256 (no timing is done here); the form is afm_grad_batch's for the same n
+ * and stride.  AFM_ERR_INVALID, with nothing enqueued, when the checkpoints,
+ * (n_cycles * steps_per_cycle / stride) x 4 x n_modes x n values (FP32 for a mixed plan, FP64
+ * otherwise), plus the segment buffer (SWEEP: stride x (2 n_modes + 1) x n values) or segment
+ * records (SEGMENTS, as afm_grad_batch states) need more than AFM_NOALLOC_SCRATCH_BYTES, or when
+ * the current device is not the plan's.  Every
+ * call on one device shares that device's array: calls that overlap in time on one device (other
+ * streams, other threads, other plans) race, so order them.  Other arguments and outputs as
+ * afm_grad_batch. */
+#define AFM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+afm_status afm_grad_batch_noalloc(afm_plan *plan, int64_t n, const double *theta,
+                                  const int32_t *n_cycles, const int32_t *target_id,
+                                  const double *targets, int32_t n_targets, double *J,
+                                  double *dJ, int32_t ckpt_stride, int32_t *status,
+                                  afm_stream_t stream);
 
 /* Initialise a swarm (Sec. 3.4): z, v drawn uniformly over the search box (z ~ U[0,1),
  * v = U[0,1) - z), pbest_z = z, pbest_J = gbest_J = +inf, gen_to_cutoff = -1, theta = SI of z.

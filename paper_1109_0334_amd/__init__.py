@@ -44,7 +44,7 @@ EXPORTS = ("afm_plan_create", "afm_plan_destroy", "afm_set_launch_shape", "afm_f
            "afm_misfit",
            "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
            "afm_forward_steady", "afm_forward_points", "afm_beam_modes", "afm_beam_shapes", "afm_last_error",
-           "afm_version", "afm_separations",
+           "afm_version", "afm_grad_batch_noalloc", "afm_separations",
            "afm_misfit_swarms", "afm_set_grad_form")
 
 
@@ -97,6 +97,7 @@ def lib() -> C.CDLL:
     L.afm_forward_batch.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
     L.afm_misfit.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, vp]
     L.afm_grad_batch.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
+    L.afm_grad_batch_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, vp, i32, vp, vp]
     L.afm_swarm_init.argtypes = [vp, C.POINTER(_Swarm), u64, vp]
     L.afm_pso_step.argtypes = [vp, C.POINTER(_Swarm), vp, u64, i32, i32, dbl, vp]
     L.afm_polish.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, vp, vp]
@@ -109,7 +110,7 @@ def lib() -> C.CDLL:
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
-              "afm_grad_batch", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
+              "afm_grad_batch", "afm_grad_batch_noalloc", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
               "afm_beam_modes", "afm_beam_shapes", "afm_forward_points", "afm_forward_steady",
               "afm_separations"):
         getattr(L, f).restype = C.c_int
@@ -375,6 +376,19 @@ class Plan:
                                     targets.shape[0], _ptr(J), _ptr(dJ), int(ckpt_stride),
                                     _ptr(status), _stream()), "afm_grad_batch")
         return J, dJ, status
+
+    def grad_batch_noalloc(self, theta, targets, J, dJ, status, target_id=None, n_cycles=None,
+                           ckpt_stride=0):
+        """afm_grad_batch_noalloc: grad_batch into caller-provided device tensors J [n],
+        dJ [n_free][n] (float64) and status [n] (int32), with the checkpoints in the library's
+        fixed scratch array (nothing is allocated on the device by the call)."""
+        n = J.shape[0]
+        tid = _dev_i32(target_id, self.device)
+        nc = _dev_i32(n_cycles, self.device)
+        _check(lib().afm_grad_batch_noalloc(self._h, n, _ptr(theta), _ptr(nc), _ptr(tid),
+                                            _ptr(targets), targets.shape[0], _ptr(J), _ptr(dJ),
+                                            int(ckpt_stride), _ptr(status), _stream()),
+               "afm_grad_batch_noalloc")
 
     def separations(self, setpoint, params=None, periods=3000, lockin=2, step=0.25e-9, rounds=6):
         """afm_separations: z_c [S] (m) at which each pixel's steady amplitude equals

@@ -26,7 +26,7 @@ SOURCES = ["forward_dmt_mixed.hip", "forward_dmt_fp64.hip", "forward_kv_mixed.hi
            "forward_hooke_mixed.hip", "forward_hooke_fp64.hip", "forward_sd_mixed.hip",
            "forward_sd_fp64.hip", "forward_none_mixed.hip", "forward_none_fp64.hip",
            "grad.hip", "api.hip", "forward.hip", "lbfgs.hip", "pso.hip", "invert.hip",
-           "modes.hip", "points.hip", "setpoint.hip"]
+           "modes.hip", "points.hip", "noalloc.hip", "setpoint.hip"]
 ARCH = os.environ.get("AFM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
