@@ -167,9 +167,14 @@ typedef struct afm_swarm {
     double *theta;           /* [D][S*P]: SI parameters of z (written by init and step)      */
 } afm_swarm;
 
-/* Build a plan: validates the problem, derives the base amplitude, initial state and the
- * non-dimensional constants, uploads the drive and lock-in tables.  precision: AFM_PREC_*.
- * Allocates device memory owned by the plan.  *out is NULL on failure. */
+/* Build a plan (the set-up of the FP, Sec. 2.2 and Sec. 3.2): validates the problem, derives
+ * the base amplitude a of Eq. 9 from the free amplitude A0 (the linear, damped steady response
+ * of Eq. 2 without tip force, summed over the modes at the tip), the initial state, and the
+ * non-dimensional constants of Eq. 2 (time in drive radians, lengths in nm, modes from Eq. 6-7
+ * and App. B), and uploads the drive and lock-in tables (the base forcing at each RK4 stage and
+ * the sin/cos weights, Sec. 3.2).  precision:
+ * AFM_PREC_*.  Allocates device memory owned by the plan.  *out is NULL on failure; the message
+ * from afm_last_error names the invalid field. */
 afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_plan **out);
 
 /* Release a plan and its device memory (synchronises the plan's private stream).  NULL is OK. */
@@ -253,8 +258,10 @@ afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_t particles
                              int32_t *status, afm_stream_t stream);
 
 /* Misfit and its exact gradient with respect to the free parameters for n points: the
- * derivative of the forward kernel's discrete RK4 trajectory and window misfit (same arithmetic
- * precision as the plan), with the state checkpointed every ckpt_stride RK4 steps.  Two forms:
+ * derivative of the forward kernel's discrete RK4 trajectory (Sec. 3.2) and window misfit
+ * (Eq. 5) -- an addition beyond the paper, whose inversion is gradient-free (Sec. 3.4); it
+ * serves the local refinement after the swarm (afm_polish).  Same arithmetic precision as the
+ * plan, with the state checkpointed every ckpt_stride RK4 steps.  Two forms:
  *   SWEEP     the discrete adjoint: per trajectory, each segment recomputed from its checkpoint
  *             and walked backwards through the transposed stage Jacobians (stages reversed);
  *             the result is independent of the stride bit for bit;
@@ -324,8 +331,10 @@ afm_status afm_swarm_init(afm_plan *plan, afm_swarm *swarm, uint64_t seed, afm_s
 afm_status afm_pso_step(afm_plan *plan, afm_swarm *swarm, const double *J, uint64_t seed,
                         int32_t iter, int32_t is_last, double cutoff, afm_stream_t stream);
 
-/* Polish n parameter points with projected L-BFGS on the discrete-adjoint gradient, in the
- * normalised coordinates of the problem's search box: history 5, H0 = s'y / y'y, trial steps
+/* Polish n parameter points with projected L-BFGS on the discrete-adjoint gradient (an
+ * addition beyond the paper's gradient-free inversion of Sec. 3.4: it minimises the same
+ * misfit, Eq. 5, from the swarm's best points, in the same search box), in the normalised
+ * coordinates of the problem's search box: history 5, H0 = s'y / y'y, trial steps
  * 2^-k (k = 0..20) of the direction evaluated together, the first satisfying Armijo (c = 1e-4)
  * accepted, a pair dropped when s'y <= 1e-12 |s||y|; a point with no acceptable step stops.
  * z: [n_free][n] normalised positions (device, in/out); params: [AFM_MAX_PARAMS][n] full

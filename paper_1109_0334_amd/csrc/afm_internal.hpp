@@ -29,6 +29,9 @@ constexpr int kMaxSteps = 4096;  // steps per drive period
 
 // Constants shared by every forward launch of a plan; passed by value as a kernel argument so
 // that they sit in scalar registers.
+// zero entries after the drive table's 2N + 1, read (never used) by the time loop's prefetch
+constexpr int kDrivePad = 8;
+
 struct KConst {
     int32_t nm;            // modes
     int32_t law;           // AFM_LAW_*
@@ -51,9 +54,9 @@ struct KConst {
     double cdamp[kMaxModes];  // w_i / (wd Q_i)
     double gain[kMaxModes];   // gamma_i
     double y0[2 * kMaxModes]; // initial (x_i, x_i') in nm
-    const float *drive_f;     // [2N + 1] g a_nm sin(pi j / N), FP32 (g = gamma_1 for a point
-                              // mass, else 1)
-    const double *drive_d;    // [2N + 1] same, FP64
+    const float *drive_f;     // [2N + 1 + kDrivePad] g a_nm sin(pi j / N), FP32 (g = gamma_1
+                              // for a point mass, else 1); the last kDrivePad entries are zero
+    const double *drive_d;    // [2N + 1 + kDrivePad] same, FP64
     const double *lock_c;     // [N + 1] cos(2 pi p / N), entry N = entry 0
     const double *lock_s;     // [N + 1] sin(2 pi p / N)
 };
@@ -111,20 +114,23 @@ constexpr int kFmFar = 3;
 constexpr int kFmBlock = 4;
 
 // Bound used by kFmBlock for a point mass: over a block of four steps of size h, every RK4 stage
-// state lies within 4h of the block's start in time, and its velocity within 4h A of the start's,
-// where A bounds |acceleration| = |-om2 (g - z_c) - cd v + F + D| at any stage state.  Out of
-// contact (gap >= dskip) |F| <= fmax = |BH| / dskip^2 and |D| <= dmax; |g - z_c| and |v| can grow
-// within the block by at most 4h (|v0| + 4h A) and 4h A, so
-//   A <= (om2 |u0| + (4h om2 + cd) |v0| + fmax + dmax) / (1 - 16 h^2 om2 - 4h cd) = A*,
-// and no stage gap falls below g0 - 4h (|v0| + 4h A*).  If that is above dskip for every lane of
-// the wave, the whole block stays out of contact (the first stage to enter contact would need a
-// larger excursion than the bound allows while all earlier stages were out of contact).  The
-// factors carry a few percent of margin and the reach an absolute 1e-3 nm, far above FP32
-// rounding of the stage arithmetic.
+// state lies within 4h of the block's start in time, and every stage velocity within 4h A of the
+// start's, where A bounds |acceleration| = |-om2 (g - z_c) - cd v + F + D| at any stage state.
+// Out of contact (gap >= dskip) |F| <= fmax = |BH| / dskip^2 and |D| <= dmax; |g - z_c| and |v|
+// can grow within the block by at most 4h (|v0| + 4h A) and 4h A, so
+//   A <= (om2 |u0| + (4h om2 + cd) |v0| + fmax + dmax) / (1 - 16 h^2 om2 - 4h cd) = A*.
+// Every stage gap is g0 plus a combination with positive weights, summing to at most 4h, of
+// stage velocities, each at least v0 - 4h A*; so no stage gap falls below
+// g0 - 4h max(0, 4h A* - v0) (v0 the signed gap rate: a tip moving away from the sample can only
+// come back by decelerating).  If that is above dskip for every lane of the wave, the whole
+// block stays out of contact (the first stage to enter contact would need a larger excursion
+// than the bound allows while all earlier stages were out of contact).  The factors carry a few
+// percent of margin and the reach an absolute 1e-3 nm, far above FP32 rounding of the stage
+// arithmetic.
 template <typename R>
 struct BlockBound {
     R c_u, c_v, c_f, c_0;  // A* = c_u |u0| + c_v |v0| + c_f fmax + c_0
-    R h4, h16;             // reach = h4 (|v0| + h16 A*) + 1e-3 nm
+    R h4, h16;             // reach = h4 max(0, h16 A* - v0) + 1e-3 nm
 };
 
 template <int LAW, typename R> struct Law;
@@ -176,13 +182,15 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
         const R av = Ops<R>::abs(v);
         const R Am = Ops<R>::fma(bb.c_u, Ops<R>::abs(g - zc),
                                  Ops<R>::fma(bb.c_v, av, Ops<R>::fma(bb.c_f, fmax, bb.c_0)));
-        const R reach = Ops<R>::fma(bb.h4, Ops<R>::fma(bb.h16, Am, av), R(1e-3));
+        const R reach = Ops<R>::fma(bb.h4, Ops<R>::max(Ops<R>::fma(bb.h16, Am, -v), R(0)), R(1e-3));
         return !(g - reach > dskip);
     }
     template <int FM> __device__ inline R add(R d, R, R b) const {
         if constexpr (std::is_same<R, float>::value) {
             if constexpr (FM == kFmFar) {
-                const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
+                // only used where every stage gap is at least dskip > a0 (the block bound), so
+                // max(d, a0) = d and this is the branch-free form's far-field piece bit for bit
+                const R r = Ops<R>::rcp(d);
                 return Ops<R>::fma(BH * r, r, b);
             } else if constexpr (FM != kFmBranch) {
                 // max(d, a0) as a median against the largest finite float (equal for every
@@ -214,7 +222,7 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
             }
         } else {
             if constexpr (FM == kFmFar) {
-                const R r = Ops<R>::rcp(Ops<R>::max(d, a0));
+                const R r = Ops<R>::rcp(d);  // d >= dskip > a0 (see the FP32 form)
                 return Ops<R>::fma(BH * r, r, b);
             } else if constexpr (FM != kFmBranch) {
                 const R r = Ops<R>::rcp(Ops<R>::max(d, a0));

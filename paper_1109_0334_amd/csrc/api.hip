@@ -124,12 +124,14 @@ static afm_status build_constants(const afm_problem &pr, int32_t precision, afm_
     }
     K.div_nm = (pr.div_limit > 0 ? pr.div_limit : 100.0) * pr.free_amplitude * 1e9;
     const int N = pr.steps_per_cycle;
-    drive_f.resize(2 * N + 1);
-    drive_d.resize(2 * N + 1);
+    // 2N + 1 entries (stage times 0, h/2, ..., 2 pi) and 8 zeros that only the time loop's
+    // one-block-ahead prefetch reads (never used in arithmetic)
+    drive_f.resize(2 * N + 1 + kDrivePad);
+    drive_d.resize(2 * N + 1 + kDrivePad);
     // a point mass takes its gain into the table (the kernel then adds the entry directly)
     const double tab_gain = pr.n_modes == 1 ? pr.gain[0] : 1.0;
-    for (int j = 0; j <= 2 * N; ++j) {
-        const double d = j == 2 * N ? 0.0 : tab_gain * a_nm * std::sin(M_PI * (double)j / (double)N);
+    for (int j = 0; j <= 2 * N + kDrivePad; ++j) {
+        const double d = j >= 2 * N ? 0.0 : tab_gain * a_nm * std::sin(M_PI * (double)j / (double)N);
         drive_d[j] = d;
         drive_f[j] = (float)d;
     }

@@ -148,36 +148,18 @@ __device__ __forceinline__ void integrate(
                 Dc = D2;
             }
         } else if (c < c_win) {
-            // four steps per pass: their nine drive entries (stage times t, t + h/2, ..., t + 4h)
-            // come in as one block of uniform loads
-            int s = 0;
-            for (; s + 4 <= N; s += 4) {
-                // scalar loads: s is wave-uniform (readfirstlane says so where a divergent exit
-                // of the enclosing loop hides it) and the table is read-only for the kernel's
-                // lifetime (the constant address space says so where the compiler cannot prove
-                // that no store of this kernel aliases it)
-                using CR = const __attribute__((address_space(4))) R;
-                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
-                const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
-                        e6 = dp[6], e7 = dp[7], e8 = dp[8];
+            // blocks of four steps, each with its nine drive entries (stage times t, t + h/2,
+            // ..., t + 4h: table entries 2s .. 2s + 8 for a block at step s)
+            auto run4 = [&](const R (&e)[9]) {
                 auto block = [&](auto fm_tag) {
                     constexpr int F = decltype(fm_tag)::value;
 #pragma unroll
-                    for (int t = 0; t < T; ++t)
-                        rk4_step<NM, COMP, F>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
-                                              h2, h6, e0, e1, e2);
+                    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-                    for (int t = 0; t < T; ++t)
-                        rk4_step<NM, COMP, F>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
-                                              h2, h6, e2, e3, e4);
-#pragma unroll
-                    for (int t = 0; t < T; ++t)
-                        rk4_step<NM, COMP, F>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
-                                              h2, h6, e4, e5, e6);
-#pragma unroll
-                    for (int t = 0; t < T; ++t)
-                        rk4_step<NM, COMP, F>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
-                                              h2, h6, e6, e7, e8);
+                        for (int t = 0; t < T; ++t)
+                            rk4_step<NM, COMP, F>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn,
+                                                  h, h2, h6, e[2 * q], e[2 * q + 1], e[2 * q + 2]);
+                    }
                 };
                 if constexpr (BLK) {
                     bool nr = false;
@@ -189,6 +171,49 @@ __device__ __forceinline__ void integrate(
                         block(std::integral_constant<int, kFmFree>());
                 } else {
                     block(std::integral_constant<int, FS>());
+                }
+            };
+            int s = 0;
+            if constexpr (BLK) {
+                // the small-batch kernel, one wave per SIMD, nothing to hide a load behind: the
+                // entries are loaded one block ahead into two alternating buffers, issued before
+                // the current block's arithmetic and consumed about a thousand cycles later.
+                // The compiler barrier after each group keeps the compiler from sinking the
+                // loads down to their use; the address is wave-uniform (all lanes read one
+                // line).  A prefetch for the block after the last reads at most entry 2N + 8,
+                // inside the table's zero padding.
+                auto load9 = [&](R (&f)[9], const R *dp) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) f[k] = dp[k];
+                    __asm__ volatile("" ::: "memory");
+                };
+                static_assert(kDrivePad >= 8, "the prefetch reads 8 entries past the table");
+                R fa[9], fb[9];
+                const R *dp = Dt;
+                load9(fa, dp);
+                for (; s + 8 <= N; s += 8, dp += 16) {
+                    load9(fb, dp + 8);
+                    run4(fa);
+                    load9(fa, dp + 16);
+                    run4(fb);
+                }
+                if (s + 4 <= N) {  // fa holds block s
+                    run4(fa);
+                    s += 4;
+                }
+            } else {
+                // many waves per SIMD hide the load: scalar loads at the top of each block (the
+                // offset is wave-uniform -- readfirstlane says so where a divergent exit of the
+                // enclosing loop hides it -- and the table is read-only for the kernel's
+                // lifetime -- the constant address space says so where the compiler cannot
+                // prove that no store of this kernel aliases it)
+                using CR = const __attribute__((address_space(4))) R;
+                for (; s + 4 <= N; s += 4) {
+                    CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                    R e[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) e[k] = dp[k];
+                    run4(e);
                 }
             }
             for (; s < N; ++s) {
@@ -930,11 +955,13 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
     }
     if (a.items) {
         // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one
-        // swarm (one separation), so they enter contact together: the wave-uniform skip form
-        // (measured 11 % faster here than the per-lane branching form)
+        // swarm (one separation), so they enter contact together: the wave-uniform skip form,
+        // tested per stage (measured 11 % faster here than the per-lane branching form, and
+        // 19 % faster than the four-step block test, whose bound is conservative; with four
+        // waves per SIMD the other waves hide each stage test's branch)
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
         const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
-        hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmBlock : kFmFree>),
+        hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree>),
                            dim3(blocks), dim3(256), 0, s, a, K);
         return hipGetLastError();
     }

@@ -790,37 +790,79 @@ __global__ void __launch_bounds__(64) k_grad_ckpt(const GradArgs A, const KConst
     }
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     float *__restrict__ ck = A.ckpt;
-    const int64_t Ntot = (int64_t)nc * N;
-    const int64_t first_w = Ntot - W + 1;
     double Jn = 0.0, Jd = 0.0;
     int32_t st = 0;
     int64_t n = 0;
-    int cdn = 0;
-    for (int c = 0; c < nc && !st; ++c) {
-        for (int s = 0; s < N; ++s, ++n) {
-            if (cdn == 0) {
-                const int64_t slot = n / kc;
+    int cdn = 0;  // steps to the next checkpoint (the state before step n is slot n / kc)
+    auto save = [&]() {
+        const int64_t slot = n / kc;
 #pragma unroll
-                for (int m = 0; m < NM; ++m) {
-                    if constexpr (MIXED) {
-                        ck[(slot * NS + m) * n_lanes + i] = x[m];
-                        ck[(slot * NS + NM + m) * n_lanes + i] = v[m];
-                        ck[(slot * NS + 2 * NM + m) * n_lanes + i] = cx[m];
-                        ck[(slot * NS + 3 * NM + m) * n_lanes + i] = cv[m];
-                    } else {
-                        double *ckd = reinterpret_cast<double *>(ck);
-                        ckd[(slot * NS + m) * n_lanes + i] = x[m];
-                        ckd[(slot * NS + NM + m) * n_lanes + i] = v[m];
-                    }
-                }
-                cdn = kc;
+        for (int m = 0; m < NM; ++m) {
+            if constexpr (MIXED) {
+                ck[(slot * NS + m) * n_lanes + i] = x[m];
+                ck[(slot * NS + NM + m) * n_lanes + i] = v[m];
+                ck[(slot * NS + 2 * NM + m) * n_lanes + i] = cx[m];
+                ck[(slot * NS + 3 * NM + m) * n_lanes + i] = cv[m];
+            } else {
+                double *ckd = reinterpret_cast<double *>(ck);
+                ckd[(slot * NS + m) * n_lanes + i] = x[m];
+                ckd[(slot * NS + NM + m) * n_lanes + i] = v[m];
             }
-            --cdn;
-            rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
-                                        Dt[2 * s + 1], Dt[2 * s + 2]);
-            if (n + 1 >= first_w) {
+        }
+    };
+    // with the stride and the period multiples of four, every checkpoint falls on the start of
+    // a four-step block: the transient periods then run in blocks whose nine drive entries come
+    // in as one group of uniform loads (the same steps and entries as one step at a time, so
+    // the same bits)
+    const bool blocks = kc % 4 == 0 && N % 4 == 0;
+    const int c_win = nc - K.lockin;  // first period of the misfit window
+    for (int c = 0; c < nc && !st; ++c) {
+        if (c < c_win && blocks) {
+            for (int s = 0; s < N; s += 4, n += 4) {
+                if (cdn == 0) {
+                    save();
+                    cdn = kc;
+                }
+                cdn -= 4;
+                // scalar loads: the offset is wave-uniform and the table read-only for the
+                // kernel's lifetime (constant address space)
+                using CR = const __attribute__((address_space(4))) R;
+                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                R e[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) e[k] = dp[k];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6,
+                                                e[2 * q], e[2 * q + 1], e[2 * q + 2]);
+            }
+        } else if (c < c_win) {
+            for (int s = 0; s < N; ++s, ++n) {
+                if (cdn == 0) {
+                    save();
+                    cdn = kc;
+                }
+                --cdn;
+                rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                            Dt[2 * s + 1], Dt[2 * s + 2]);
+            }
+        } else {
+            // window period: the state after every step is a sample; step n's target entry is
+            // n + 1 - first_w = w0 + s, loaded one step ahead
+            const int64_t w0 = (int64_t)(c - c_win) * N;
+            double Un = Urow[w0];
+            for (int s = 0; s < N; ++s, ++n) {
+                if (cdn == 0) {
+                    save();
+                    cdn = kc;
+                }
+                --cdn;
+                const double Uc = Un;
+                Un = Urow[w0 + s + 1 < W ? w0 + s + 1 : w0 + s];
+                rk4_step<NM, COMP, kFmFree>(law, x, v, cx, cv, om2, cd, gn, h, h2, h6, Dt[2 * s],
+                                            Dt[2 * s + 1], Dt[2 * s + 2]);
                 const double u = sample<NM, COMP>(x, cx, zc);
-                const double U = Urow[n + 1 - first_w] * 1e9;
+                const double U = Uc * 1e9;
                 const double e = U - u;
                 Jn = __builtin_fma(e, e, Jn);
                 Jd = __builtin_fma(U, U, Jd);
