@@ -143,7 +143,7 @@ __device__ __forceinline__ void integrate(
             for (int s = 0; s < N; ++s) {
                 const double j = jb + 2.0 * s;
                 const R D1 = dv.at(j + 1.0), D2 = dv.at(j + 2.0);
-                rk4_step<NM, COMP, FM>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
+                rk4_step<NM, COMP, FS>(law[0], x[0], v[0], cx[0], cv[0], om2, cd, gn, h, h2, h6,
                                        Dc, D1, D2);
                 Dc = D2;
             }
@@ -168,7 +168,7 @@ __device__ __forceinline__ void integrate(
                     if (__builtin_amdgcn_ballot_w64(nr) == 0)
                         block(std::integral_constant<int, kFmFar>());
                     else
-                        block(std::integral_constant<int, kFmFree>());
+                        block(std::integral_constant<int, FS>());
                 } else {
                     block(std::integral_constant<int, FS>());
                 }
@@ -253,7 +253,7 @@ __device__ __forceinline__ void integrate(
                     for (int t = 0; t < T; ++t) {
                         const double Uc = Un[t];
                         if (Up[t]) Un[t] = Up[t][s + 1 < N ? s + 1 : s];
-                        rk4_step<NM, COMP, FM>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
+                        rk4_step<NM, COMP, FS>(law[t], x[t], v[t], cx[t], cv[t], om2, cd, gn, h,
                                                h2, h6, D0, D1, D2);
                         // explicit fmas: with contraction left to the compiler, instantiations
                         // that differ only in lanes per trajectory could round differently
@@ -956,8 +956,9 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
     if (a.items) {
         // persistent grid: 4 waves per SIMD on every CU.  All lanes of a wave belong to one
         // swarm (one separation), so they enter contact together: the wave-uniform skip form,
-        // tested per stage (measured 11 % faster here than the per-lane branching form, and
-        // 19 % faster than the four-step block test, whose bound is conservative; with four
+        // tested per stage (measured 11 % faster here than the per-lane branching form, 19 %
+        // faster than the four-step block test, whose bound is conservative, and 8 % faster
+        // than the block test with per-stage skips inside the blocks near contact; with four
         // waves per SIMD the other waves hide each stage test's branch)
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
         const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;

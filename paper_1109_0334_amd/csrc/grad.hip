@@ -15,6 +15,8 @@
 // accumulated across steps in FP64 (so the result is independent of the checkpoint stride), and
 // are mapped to SI parameter derivatives by the chain rule at the end.
 // Buffers are structure-of-arrays over lanes ([slot][variable][n]) so every access coalesces.
+#include <cmath>
+
 #include "rk4.hpp"
 
 namespace afm {
@@ -733,8 +735,11 @@ __global__ void __launch_bounds__(64) k_grad_mp(const GradArgs A, const KConst K
 // (trajectory, segment) pair its own lane, which recomputes the segment from its checkpoint and
 // carries the 2 NM + NC + 1 tangent columns of (Phi_s, S_s) forward through the RK4 stages (the
 // same stage states and force partials as the reverse sweep), accumulating c_s and p_s from the
-// window samples in FP64, and k_grad_combine runs the short backward recursion over the segments
-// in FP64, one lane per trajectory.  Tangents are in deflection coordinates (mode 1's state is
+// window samples in FP64, k_grad_compose folds each group of B consecutive segments into one
+// record of the same form (the recursion over the group applied to a symbolic lambda at the
+// group's end: an affine map, composed in FP64 by one lane per (trajectory, group)), and
+// k_grad_combine runs the short backward recursion over the groups in FP64, one lane per
+// trajectory.  Tangents are in deflection coordinates (mode 1's state is
 // the gap g = z_c + u_1, but z_c is a parameter of the map: the z_c column moves the gap at fixed
 // deflection), matching the reverse sweep's dJ/dz_c.  The result is the same exact derivative as
 // the reverse sweep up to rounding (it depends on the stride only through rounding).
@@ -1059,8 +1064,98 @@ __global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst
     for (int t = 0; t < NT; ++t) rec[(int64_t)(f++) * n_lanes] = acc[t];
 }
 
+// Fold segments g B .. min((g + 1) B, n_seg) - 1 of a trajectory into one record, written over
+// the group's first record: with lambda = alpha + Bm lambda_end carried backwards from the
+// identity map at the group's end, each segment gives alpha' = c_s + Phi_s^T alpha,
+// Bm' = Phi_s^T Bm (state rows) and adds p_s + S_s^T alpha, S_s^T Bm to the parameter rows; the
+// result has the record layout with (Bm, parameter matrix) for (Phi^T, S^T) and (alpha, parameter
+// constant) for (c, p).  One lane per (trajectory, group); the lane reads the group's records
+// last to first and writes only after reading the first, so groups never overlap.
 template <int LAW, int NM, bool MIXED>
-__global__ void __launch_bounds__(64) k_grad_combine(const GradArgs A, const KConst K) {
+__global__ void __launch_bounds__(64) k_grad_compose(const GradArgs A, const KConst K, int B) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr int NY = 2 * NM;
+    constexpr int NP = L::NC + 1;
+    constexpr int NT = NY + NP;
+    constexpr int NF = seg_fields<NM, NP>();
+    const int64_t n_lanes = A.n;
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = l % n_lanes, gi = l / n_lanes;
+    const int64_t nseg_max = ((int64_t)K.n_cycles * K.N + A.kc - 1) / A.kc;
+    if (gi >= (nseg_max + B - 1) / B) return;
+    if (A.status[i] != 0) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int64_t nseg = ((int64_t)nc * K.N + A.kc - 1) / A.kc;
+    const int64_t s0 = gi * B;
+    if (s0 >= nseg) return;
+    const int64_t s1 = s0 + B < nseg ? s0 + B : nseg;
+    if (s1 - s0 < 2) return;  // a one-segment group is its own record
+    double *recs = reinterpret_cast<double *>(A.seg) + n_lanes;
+    double al[NY], bm[NY][NY], ga[NP], gm[NP][NY];
+#pragma unroll
+    for (int r = 0; r < NY; ++r) {
+        al[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NY; ++k) bm[r][k] = r == k ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+        ga[t] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NY; ++k) gm[t][k] = 0.0;
+    }
+    for (int64_t sgi = s1 - 1; sgi >= s0; --sgi) {
+        const double *rec = recs + sgi * NF * n_lanes + i;
+        auto at = [&](int f) { return rec[(int64_t)f * n_lanes]; };
+        double na[NY], nb[NY][NY];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double m[NY];
+#pragma unroll
+            for (int r = 0; r < NY; ++r) m[r] = at(t * NY + r);
+            double d = at(NT * NY + t);
+#pragma unroll
+            for (int r = 0; r < NY; ++r) d = __builtin_fma(m[r], al[r], d);
+            double row[NY];
+#pragma unroll
+            for (int k = 0; k < NY; ++k) {
+                double e = 0.0;
+#pragma unroll
+                for (int r = 0; r < NY; ++r) e = __builtin_fma(m[r], bm[r][k], e);
+                row[k] = e;
+            }
+            if (t < NY) {
+                na[t] = d;
+#pragma unroll
+                for (int k = 0; k < NY; ++k) nb[t][k] = row[k];
+            } else {
+                ga[t - NY] += d;
+#pragma unroll
+                for (int k = 0; k < NY; ++k) gm[t - NY][k] += row[k];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            al[r] = na[r];
+#pragma unroll
+            for (int k = 0; k < NY; ++k) bm[r][k] = nb[r][k];
+        }
+    }
+    double *out = recs + s0 * NF * n_lanes + i;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int k = 0; k < NY; ++k)
+            out[(int64_t)(t * NY + k) * n_lanes] = t < NY ? bm[t][k] : gm[t - NY][k];
+        out[(int64_t)(NT * NY + t) * n_lanes] = t < NY ? al[t] : ga[t - NY];
+    }
+}
+
+// Backward recursion over the trajectory's records, every B-th (the composed groups).
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad_combine(const GradArgs A, const KConst K, int B) {
     using R = typename std::conditional<MIXED, float, double>::type;
     using L = Law<LAW, R>;
     constexpr int NY = 2 * NM;
@@ -1080,7 +1175,7 @@ __global__ void __launch_bounds__(64) k_grad_combine(const GradArgs A, const KCo
     for (int r = 0; r < NY; ++r) lam[r] = 0.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) g[k] = 0.0;
-    for (int64_t sgi = nseg - 1; sgi >= 0; --sgi) {
+    for (int64_t sgi = (nseg - 1) / B * B; sgi >= 0; sgi -= B) {
         const double *rec = recs + sgi * NF * n_lanes + i;
         auto at = [&](int f) { return rec[(int64_t)f * n_lanes]; };
         double nl[NY];
@@ -1132,8 +1227,20 @@ hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
                                dim3(256), 0, s, a, K);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
+            // groups of about sqrt(n_seg) segments: n x n_seg / B composing lanes, then B-fold
+            // fewer sequential steps per trajectory
+            int B = 1;
+            if (nseg >= 16) {
+                B = (int)std::ceil(std::sqrt((double)nseg));
+                const int64_t groups = (nseg + B - 1) / B;
+                hipLaunchKernelGGL((k_grad_compose<LAW, NM, MIXED>),
+                                   dim3((unsigned)((a.n * groups + 63) / 64)), dim3(64), 0, s, a,
+                                   K, B);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
             hipLaunchKernelGGL((k_grad_combine<LAW, NM, MIXED>),
-                               dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, s, a, K);
+                               dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, s, a, K, B);
             return hipGetLastError();
         }
     }
