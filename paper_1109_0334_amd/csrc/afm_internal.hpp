@@ -178,6 +178,12 @@ template <typename R> struct Law<AFM_LAW_DMT, R> {
     // kFmBlock: whether the gap g (rate v) may come within dskip during the next four steps
     // (see BlockBound); NaN states count as near
     static constexpr bool kBlock = true;
+    // ordering key of the small-batch kernel's lanes: trajectories with similar contact
+    // stiffness E* sqrt(R) tap at similar phases, so a wave of them is near contact in fewer
+    // four-step blocks (any order gives the same results)
+    __host__ __device__ static double contact_key(const double *p) {
+        return p[2] * ::sqrt(::fabs(p[4]));
+    }
     __device__ inline bool near(R g, R v, const BlockBound<R> &bb) const {
         const R av = Ops<R>::abs(v);
         const R Am = Ops<R>::fma(bb.c_u, Ops<R>::abs(g - zc),
@@ -531,6 +537,9 @@ struct FwdArgs {
     int64_t mtrace_ld;         // (trajectory fastest)
     int32_t *periods;          // optional periods integrated per trajectory
     int32_t xcd_stride;        // plain k_forward grid: > 1 = only every xcd_stride-th workgroup works
+    const int32_t *order;      // plain k_forward: lane slot -> trajectory (NULL = identity)
+    int32_t *order_buf;        // plan-owned [kOrderMax] buffers the launcher may use to build
+    double *key_buf;           // `order` (NULL = do not reorder)
 };
 
 // Adjoint launch description (see afm_grad_batch).
@@ -588,6 +597,8 @@ struct afm_plan {
     float *d_drive_f = nullptr;
     double *d_drive_d = nullptr;
     double *d_lock = nullptr;       // [2 (N + 1)]
+    int32_t *d_order = nullptr;     // [kOrderMax] lane order of small forward batches
+    double *d_order_keys = nullptr; // [kOrderMax] their keys
     hipStream_t stream = nullptr;   // private stream used to capture and replay graphs
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // plan-owned workspace for afm_invert
@@ -659,6 +670,8 @@ hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a
 // Batches at and above this many trajectories are treated as GPU-filling (four-wave blocks,
 // per-lane branching force law); below it one wave owns a SIMD.
 constexpr int64_t kSmallBatch = 65536;
+// largest small batch whose lanes are ordered by the law's contact key (see launch_plain)
+constexpr int64_t kOrderMax = 16384;
 // the forward kernels of one force law and precision (forward_impl.hpp, instantiated by the
 // forward_<law>_<precision>.hip units)
 template <int LAW, bool MIXED>

@@ -191,6 +191,8 @@ afm_status afm_plan_create(const afm_problem *problem, int32_t precision, afm_pl
     if (e == hipSuccess) e = hipMalloc(&plan->d_drive_f, df.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&plan->d_drive_d, dd.size() * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&plan->d_lock, lk.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&plan->d_order, kOrderMax * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&plan->d_order_keys, kOrderMax * sizeof(double));
     if (e == hipSuccess) e = hipMemcpy(plan->d_drive_f, df.data(), df.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(plan->d_drive_d, dd.data(), dd.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(plan->d_lock, lk.data(), lk.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -247,6 +249,8 @@ afm_status afm_plan_destroy(afm_plan *plan) {
     if (plan->d_drive_f) (void)hipFree(plan->d_drive_f);
     if (plan->d_drive_d) (void)hipFree(plan->d_drive_d);
     if (plan->d_lock) (void)hipFree(plan->d_lock);
+    if (plan->d_order) (void)hipFree(plan->d_order);
+    if (plan->d_order_keys) (void)hipFree(plan->d_order_keys);
     if (plan->ev_in) (void)hipEventDestroy(plan->ev_in);
     if (plan->ev_out) (void)hipEventDestroy(plan->ev_out);
     if (plan->stream) (void)hipStreamDestroy(plan->stream);

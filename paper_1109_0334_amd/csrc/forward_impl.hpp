@@ -415,10 +415,11 @@ __global__ void __launch_bounds__(256) k_forward(const FwdArgs A, const KConst K
     for (int t = 0; t < T; ++t) {
         ii[t] = i0 + (int64_t)t * blockDim.x;
         act[t] = ii[t] < A.n;
+        if (A.order && act[t]) ii[t] = A.order[ii[t]];  // lane slot -> trajectory
     }
     int nc = K.n_cycles;
     if constexpr (T == 1) {
-        const int64_t grp = A.group > 0 ? i0 / A.group : i0;
+        const int64_t grp = A.group > 0 ? ii[0] / A.group : ii[0];
         if (A.n_cycles) nc = A.n_cycles[grp];
     }
     lane_forward<LAW, NM, MIXED, FM, T, DP, EX>(A, K, ii, act, nc);
@@ -870,6 +871,42 @@ constexpr int kXcds = 8;
 constexpr int kCusPerXcd = 32;
 
 // Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
+// Lane order of a small batch: the law's contact key of every trajectory (NaN ordered last) ...
+template <int LAW>
+__global__ void __launch_bounds__(256) k_order_keys(const FwdArgs A, const KConst K) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const double k = Law<LAW, double>::contact_key(p);
+    A.key_buf[i] = k == k ? k : INFINITY;
+}
+
+// ... and its rank: order[rank(i)] = i, ranks by (key, index), so ties (and infinities) keep
+// their index order and the ranks are a permutation of 0 .. n - 1.  Keys pass through LDS in
+// tiles of the workgroup's size; every lane of a workgroup takes part in every tile.
+__global__ void __launch_bounds__(256) k_order_rank(int32_t n, const double *keys, int32_t *order) {
+    __shared__ double tile[256];
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    const double ki = i < n ? keys[i] : 0.0;
+    int32_t r = 0;
+    for (int32_t b0 = 0; b0 < n; b0 += 256) {
+        const int32_t j = b0 + (int32_t)threadIdx.x;
+        tile[threadIdx.x] = j < n ? keys[j] : INFINITY;
+        __syncthreads();
+        // a full tile of 256: padding entries are +inf at indices >= n, above every lane's
+        // index, so no padding entry is ordered before a lane
+#pragma unroll 8
+        for (int32_t k = 0; k < 256; ++k) {
+            const double kj = tile[k];
+            r += (kj < ki || (kj == ki && b0 + k < i)) ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    if (i < n) order[r] = i;
+}
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
@@ -889,6 +926,24 @@ hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStre
     const int64_t nb = (a0.n + per_block - 1) / per_block;
     FwdArgs a = a0;
     a.xcd_stride = nb <= kCusPerXcd ? kXcds : 1;
+    if constexpr (NM == 1 &&
+                  HasBlock<Law<LAW, typename std::conditional<MIXED, float, double>::type>>::value) {
+        // the block-level contact test runs a block without the contact piece only when no lane
+        // of the wave can reach contact in it: waves of trajectories ordered by contact key
+        // (similar stiffness, similar tapping phase) clear the test in more blocks.  Only the
+        // assignment of trajectories to lanes changes, never a result.
+        if (!large && a0.order_buf && a0.key_buf && a0.n > 64 && a0.n <= kOrderMax) {
+            const dim3 g((unsigned)((a0.n + 255) / 256));
+            hipLaunchKernelGGL((k_order_keys<LAW>), g, dim3(256), 0, s, a0, K);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_order_rank, g, dim3(256), 0, s, (int32_t)a0.n,
+                               (const double *)a0.key_buf, a0.order_buf);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            a.order = a0.order_buf;
+        }
+    }
     const dim3 grid((unsigned)(nb * a.xcd_stride));
     if constexpr (NM == 1) {
         if (sh.tpl == 2) {
@@ -966,12 +1021,15 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
                            dim3(blocks), dim3(256), 0, s, a, K);
         return hipGetLastError();
     }
+    FwdArgs ao = a;  // the plan's lane-order buffers for small batches
+    ao.order_buf = plan->d_order;
+    ao.key_buf = plan->d_order_keys;
     FwdShape sh;
-    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, a, NM, s,
-                                 [&](FwdShape c) { return launch_plain<LAW, NM, MIXED>(a, K, c, s); },
+    hipError_t e = forward_shape(plan, MIXED ? AFM_PREC_MIXED : AFM_PREC_FP64, ao, NM, s,
+                                 [&](FwdShape c) { return launch_plain<LAW, NM, MIXED>(ao, K, c, s); },
                                  &sh);
     if (e != hipSuccess) return e;
-    return launch_plain<LAW, NM, MIXED>(a, K, sh, s);
+    return launch_plain<LAW, NM, MIXED>(ao, K, sh, s);
 }
 
 template <int LAW, bool MIXED>

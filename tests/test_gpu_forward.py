@@ -323,6 +323,29 @@ def test_launch_shapes_bit_identical(afm, orc, precision, n, nc):
         assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [65, 1000, 16384, 16385])
+def test_lane_order_is_invisible(afm, n):
+    """The small-batch kernel assigns trajectories to lanes in contact-key order (65 to 16384
+    trajectories; 16385 runs unordered): permuting the inputs permutes the outputs bit for bit,
+    and equal keys (duplicated parameter columns) still cover every trajectory once."""
+    import torch
+
+    c = W.config("c2")
+    m = dict(c["model"], n_cycles=40)
+    plan = _plan(afm, c, "mixed", model=m)
+    th = _theta(c, n, 70 + n)
+    th[:, : n // 4] = th[:, n // 4: 2 * (n // 4)]  # ties in the ordering key
+    perm = np.random.default_rng(n).permutation(n)
+    a = plan.forward_batch(torch.tensor(th, device="cuda"))
+    b = plan.forward_batch(torch.tensor(np.ascontiguousarray(th[:, perm]), device="cuda"))
+    for k in ("amp", "phase", "status"):
+        x, y = a[k].cpu().numpy(), b[k].cpu().numpy()
+        assert np.array_equal(x[perm].view(np.uint8), y.view(np.uint8)), k
+    st = a["status"].cpu().numpy()
+    assert np.isin(st, [0, 1, 2]).all() and (st == 0).mean() > 0.9  # every slot written
+
+
 @pytest.mark.parametrize("nm,law", [(2, "dmt"), (3, "kv"), (4, "kv"), (5, "dmt"), (6, "kv"),
                                     (7, "kv"), (8, "kv")])
 def test_mode_parallel_bit_identical(afm, orc, nm, law):
