@@ -675,7 +675,9 @@ __global__ void __launch_bounds__(256) k_forward_queue(const FwdArgs A, const KC
         int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
         nc = __builtin_amdgcn_readfirstlane(nc);
         if (local < A.group) {
-            const int64_t ii[1] = {grp * A.group + local};
+            int64_t ti = grp * A.group + local;
+            if (A.order) ti = A.order[ti];  // lane slot -> trajectory of the same swarm
+            const int64_t ii[1] = {ti};
             const bool act[1] = {true};
             lane_forward<LAW, NM, MIXED, FM, 1, false, EX>(A, K, ii, act, nc);
         }
@@ -907,6 +909,24 @@ __global__ void __launch_bounds__(256) k_order_rank(int32_t n, const double *key
     if (i < n) order[r] = i;
 }
 
+// Lane order within each swarm of a work-queue batch: order[g seg + rank] = i for the
+// trajectories i of swarm g (segment [g seg, (g + 1) seg)), ranked by (key, index) like
+// k_order_rank.  The segment's keys are read by every lane of a wave alike.
+__global__ void __launch_bounds__(256) k_order_rank_seg(int64_t n, int32_t seg, const double *keys,
+                                                       int32_t *order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g0 = i / seg * seg;
+    const int64_t g1 = g0 + seg < n ? g0 + seg : n;
+    const double ki = keys[i];
+    int32_t r = 0;
+    for (int64_t j = g0; j < g1; ++j) {
+        const double kj = keys[j];
+        r += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    order[g0 + r] = (int32_t)i;
+}
+
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
@@ -1015,10 +1035,27 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
         // faster than the four-step block test, whose bound is conservative, and 8 % faster
         // than the block test with per-stage skips inside the blocks near contact; with four
         // waves per SIMD the other waves hide each stage test's branch)
+        FwdArgs aq = a;
+        if constexpr (NM == 1 && HasBlock<Law<LAW, float>>::value) {
+            // the skip form leaves the contact piece out of a stage only when no lane of the
+            // wave is near contact: within each swarm, the particles go to lanes in
+            // contact-key order, so that a wave holds particles of similar stiffness
+            if (a.order_buf && a.key_buf && a.group > 64) {
+                const dim3 g((unsigned)((a.n + 255) / 256));
+                hipLaunchKernelGGL((k_order_keys<LAW>), g, dim3(256), 0, s, a, K);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_order_rank_seg, g, dim3(256), 0, s, a.n, a.group,
+                                   (const double *)a.key_buf, a.order_buf);
+                e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                aq.order = a.order_buf;
+            }
+        }
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
         const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
         hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree>),
-                           dim3(blocks), dim3(256), 0, s, a, K);
+                           dim3(blocks), dim3(256), 0, s, aq, K);
         return hipGetLastError();
     }
     FwdArgs ao = a;  // the plan's lane-order buffers for small batches

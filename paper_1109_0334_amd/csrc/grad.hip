@@ -962,13 +962,18 @@ __global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     // tangent columns: NY state columns (unit start), NP parameter columns (zero start)
     constexpr int NT = NY + NP;
-    R tx[NT][NM], tv[NT][NM];
+    // (with compensated updates in FP32, as the state: the unit start makes every increment
+    // small against the column, and rounding each step against it would bias the segment's
+    // map by about the stride times the unit roundoff)
+    R tx[NT][NM], tv[NT][NM], ctx[NT][NM], ctv[NT][NM];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
             tx[t][m] = (t == m) ? R(1) : R(0);
             tv[t][m] = (t == NM + m) ? R(1) : R(0);
+            ctx[t][m] = R(0);
+            ctv[t][m] = R(0);
         }
     double acc[NT];
 #pragma unroll
@@ -1030,8 +1035,19 @@ __global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst
             for (int m = 0; m < NM; ++m) {
                 const R sx = tv[t][m] + R(2) * (Vt2[m] + Vt3[m]) + Vt4[m];
                 const R sv = e1[m] + R(2) * (e2[m] + e3[m]) + e4[m];
-                tx[t][m] = Ops<R>::fma(h6, sx, tx[t][m]);
-                tv[t][m] = Ops<R>::fma(h6, sv, tv[t][m]);
+                if constexpr (COMP) {
+                    const R dx = Ops<R>::fma(h6, sx, -ctx[t][m]);
+                    const R ux = tx[t][m] + dx;
+                    ctx[t][m] = (ux - tx[t][m]) - dx;
+                    tx[t][m] = ux;
+                    const R dv = Ops<R>::fma(h6, sv, -ctv[t][m]);
+                    const R uv = tv[t][m] + dv;
+                    ctv[t][m] = (uv - tv[t][m]) - dv;
+                    tv[t][m] = uv;
+                } else {
+                    tx[t][m] = Ops<R>::fma(h6, sx, tx[t][m]);
+                    tv[t][m] = Ops<R>::fma(h6, sv, tv[t][m]);
+                }
             }
         }
         // the state itself, bit for bit as the forward pass stepped it
@@ -1043,7 +1059,7 @@ __global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst
             for (int t = 0; t < NT; ++t) {
                 double du = 0.0;
 #pragma unroll
-                for (int m = 0; m < NM; ++m) du += (double)tx[t][m];
+                for (int m = 0; m < NM; ++m) du += (double)tx[t][m] - (double)ctx[t][m];
                 acc[t] = __builtin_fma(ub, du, acc[t]);
             }
         }
@@ -1056,9 +1072,11 @@ __global__ void __launch_bounds__(256) k_grad_tan(const GradArgs A, const KConst
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
-        for (int m = 0; m < NM; ++m) rec[(int64_t)(f++) * n_lanes] = (double)tx[t][m];
+        for (int m = 0; m < NM; ++m)
+            rec[(int64_t)(f++) * n_lanes] = (double)tx[t][m] - (double)ctx[t][m];
 #pragma unroll
-        for (int m = 0; m < NM; ++m) rec[(int64_t)(f++) * n_lanes] = (double)tv[t][m];
+        for (int m = 0; m < NM; ++m)
+            rec[(int64_t)(f++) * n_lanes] = (double)tv[t][m] - (double)ctv[t][m];
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) rec[(int64_t)(f++) * n_lanes] = acc[t];

@@ -40,6 +40,7 @@ struct WsLayout {
     size_t z, v, pbest_z, theta, pbest_J, J, gbest_z, gbest_J, gen, status;
     size_t taken, zsel, tsel, nsel, Jsel, bsel, polish;  // polish of the top-k (if requested)
     size_t items, head;                                  // persistent queue (uneven periods)
+    size_t order, keys;                                  // lane order within each swarm
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -65,6 +66,8 @@ WsLayout layout(const afm_plan *plan, int32_t D, int32_t S, int32_t P, int32_t k
     L.status = take(sizeof(int32_t) * n);
     L.items = take(sizeof(int32_t) * (size_t)S * ((P + 63) / 64));
     L.head = take(sizeof(int32_t));
+    L.order = take(sizeof(int32_t) * n);
+    L.keys = take(sizeof(double) * n);
     if (k > 0) {
         const size_t m = (size_t)S * k;
         L.taken = take(sizeof(int32_t) * n);
@@ -183,6 +186,8 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
             a.n_items = n_items;
             a.chunks = chunks;
             a.head = (int32_t *)(ws + L.head);
+            a.order_buf = (int32_t *)(ws + L.order);
+            a.key_buf = (double *)(ws + L.keys);
         }
         a.J = J;
         a.status = status;
@@ -289,7 +294,12 @@ extern "C" afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_
     a.status = status;
     hipError_t e;
     if (n_cycles) {
-        const size_t bytes = sizeof(int32_t) * ((size_t)n_items + 64);
+        // [items, padded to 64][head, 64][lane order, n][keys, n doubles]
+        const size_t n = (size_t)n_swarms * particles;
+        const size_t off_head = ((size_t)n_items + 63) / 64 * 64;
+        const size_t off_order = off_head + 64;
+        const size_t off_keys = (off_order + n + 1) / 2 * 2;  // 8-byte aligned, in int32 units
+        const size_t bytes = sizeof(int32_t) * (off_keys + 2 * n);
         const bool hit = plan->q_ncyc == n_cycles && plan->q_S == n_swarms &&
                          plan->q_P == particles && plan->qws_bytes >= bytes;
         if (!hit) {
@@ -320,7 +330,9 @@ extern "C" afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_
         a.items = (const int32_t *)plan->qws;
         a.n_items = n_items;
         a.chunks = chunks;
-        a.head = (int32_t *)plan->qws + ((n_items + 63) / 64) * 64;
+        a.head = (int32_t *)plan->qws + off_head;
+        a.order_buf = (int32_t *)plan->qws + off_order;
+        a.key_buf = reinterpret_cast<double *>((int32_t *)plan->qws + off_keys);
     }
     e = launch_forward(plan, a, (hipStream_t)stream);
     return e == hipSuccess ? AFM_OK : hip_fail(e, "afm_misfit_swarms launch");
