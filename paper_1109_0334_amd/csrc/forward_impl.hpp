@@ -1053,7 +1053,18 @@ hipError_t launch_t(const afm_plan *plan, const FwdArgs &a, const KConst &K, hip
             }
         }
         hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head);
-        const unsigned blocks = (unsigned)(plan->n_cu > 0 ? plan->n_cu : 256) * 4;
+        const int n_cu = plan->n_cu > 0 ? plan->n_cu : 256;
+        const unsigned blocks = (unsigned)n_cu * 4;
+        if constexpr (NM == 1 && HasBlock<Law<LAW, float>>::value) {
+            // no more items than SIMDs: a wave per SIMD at most, where the per-stage branch
+            // stalls a lone wave and the block-level test runs far blocks without it (the same
+            // bits; see launch_plain)
+            if ((int64_t)a.n_items <= (int64_t)n_cu * 4) {
+                hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, kFmBlock>), dim3(blocks),
+                                   dim3(256), 0, s, aq, K);
+                return hipGetLastError();
+            }
+        }
         hipLaunchKernelGGL((k_forward_queue<LAW, NM, MIXED, branchy ? kFmSkip : kFmFree>),
                            dim3(blocks), dim3(256), 0, s, aq, K);
         return hipGetLastError();
