@@ -391,9 +391,10 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
     const int32_t form_default = tuned ? plan->tuned_form : grad_default_form(plan);
     if (ckpt_stride > 0) return run_grad(plan, a, ckpt_stride, mp_default, form_default, s);
     if (tuned) return run_grad(plan, a, plan->tuned_kc, plan->tuned_mp, plan->tuned_form, s);
-    // autotune: time each candidate stride and form (the reverse sweep -- with several modes one
-    // lane per trajectory or one lane per mode -- and the segment-parallel form) on this call's
-    // inputs, keep the fastest; candidates needing more than 8 GiB of workspace are left out
+    // autotune: time each candidate stride and form (the reverse sweep and the segment-parallel
+    // form, with several modes each with one lane per trajectory or one lane per mode for the
+    // passes along the trajectory) on this call's inputs, keep the fastest; candidates needing
+    // more than 8 GiB of workspace are left out
     struct Cand { int32_t kc, mp, form; };
     std::vector<Cand> cand;
     for (int32_t kc : {16, 64, 256}) {
@@ -404,7 +405,10 @@ afm_status afm_grad_batch(afm_plan *plan, int64_t n, const double *theta, const 
         if (plan->grad_form != kGradSweep && grad_segments_ok(plan) &&
             grad_seg_bytes(plan, plan->precision, n, kc, kGradSegments) +
                     grad_ckpt_bytes(plan, plan->precision, n, kc) <= ((size_t)8 << 30))
+        {
             cand.push_back({kc, 0, kGradSegments});
+            if (plan->kc.nm > 1) cand.push_back({kc, 1, kGradSegments});
+        }
     }
     if (cand.empty()) cand.push_back({256, 0, kGradSweep});
     hipEvent_t e0, e1;

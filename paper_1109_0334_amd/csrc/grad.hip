@@ -889,6 +889,143 @@ __global__ void __launch_bounds__(64) k_grad_ckpt(const GradArgs A, const KConst
     coef_out[i] = -2.0 / Jd;  // dJ/du_n = coef (U_n - u_n)
 }
 
+// k_grad_ckpt with one lane per mode (the mode-parallel forward of k_grad_mp): G lanes per
+// trajectory, lane q integrating mode q with the shared force, the same operations in the same
+// order as one lane per trajectory (so the same checkpoints, J and status bit for bit); lanes
+// without a mode carry zeros.  For small multi-mode batches, where one lane per trajectory
+// leaves most SIMDs idle.
+template <int LAW, int NM, bool MIXED>
+__global__ void __launch_bounds__(64) k_grad_ckpt_mp(const GradArgs A, const KConst K) {
+    using R = typename std::conditional<MIXED, float, double>::type;
+    using L = Law<LAW, R>;
+    constexpr bool COMP = MIXED;
+    constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
+    constexpr int NS = 4 * NM;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (i >= A.n) return;  // whole groups (block size a multiple of 8)
+    const int q = threadIdx.x & (G - 1);
+    const int gbase = (int)(threadIdx.x & 63) & ~(G - 1);
+    const bool real = q < NM;
+    const int64_t grp = A.group > 0 ? i / A.group : i;
+    double p[kMaxParams];
+    load_params(p, K, A.base, A.base_ld, grp, A.theta, A.ld, i);
+    const L law(p, K);
+    const double zc = p[0] * 1e9;
+    const int nc = A.n_cycles ? A.n_cycles[grp] : K.n_cycles;
+    const int N = K.N;
+    const int64_t W = (int64_t)K.lockin * N;
+    const int64_t row = A.target_id ? (int64_t)A.target_id[grp] : 0;
+    const int kc = A.kc;
+    const int64_t n_lanes = A.n;
+    double *coef_out = reinterpret_cast<double *>(A.seg);
+    auto fail = [&](int32_t st) {
+        if (q != 0) return;
+        A.J[i] = INFINITY;
+        for (int j = 0; j < K.n_free; ++j) A.dJ[(int64_t)j * A.ld + i] = NAN;
+        A.status[i] = st;
+        coef_out[i] = 0.0;
+    };
+    if (nc < K.lockin || nc > K.n_cycles || row < 0 || row >= A.n_targets) {
+        fail(AFM_ST_BAD_INPUT);
+        return;
+    }
+    const double *__restrict__ Urow = A.targets + row * W;
+    const R *__restrict__ Dt;
+    if constexpr (MIXED) Dt = K.drive_f;
+    else Dt = K.drive_d;
+    ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
+    R x = R(0), v = R(0), cx = R(0), cv = R(0);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        if (q == m) {
+            ml.om2 = (R)K.om2[m];
+            ml.cd = (R)K.cdamp[m];
+            ml.gn = (R)K.gain[m];
+            ml.zoff = m == 0 ? law.zc : R(0);
+            ml.w = R(1);
+            x = (R)(m == 0 ? zc + K.y0[0] : K.y0[m]);
+            v = (R)K.y0[NM + m];
+        }
+    }
+    const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    float *__restrict__ ck = A.ckpt;
+    double Jn = 0.0, Jd = 0.0;
+    int32_t st = 0;
+    int64_t n = 0;
+    int cdn = 0;  // steps to the next checkpoint (the state before step n is slot n / kc)
+    auto save = [&]() {
+        if (!real) return;
+        const int64_t slot = n / kc;
+        if constexpr (MIXED) {
+            ck[(slot * NS + q) * n_lanes + i] = x;
+            ck[(slot * NS + NM + q) * n_lanes + i] = v;
+            ck[(slot * NS + 2 * NM + q) * n_lanes + i] = cx;
+            ck[(slot * NS + 3 * NM + q) * n_lanes + i] = cv;
+        } else {
+            double *ckd = reinterpret_cast<double *>(ck);
+            ckd[(slot * NS + q) * n_lanes + i] = x;
+            ckd[(slot * NS + NM + q) * n_lanes + i] = v;
+        }
+    };
+    const bool blocks = kc % 4 == 0 && N % 4 == 0;
+    const int c_win = nc - K.lockin;
+    for (int c = 0; c < nc && !st; ++c) {
+        if (c < c_win && blocks) {
+            for (int s = 0; s < N; s += 4, n += 4) {
+                if (cdn == 0) {
+                    save();
+                    cdn = kc;
+                }
+                cdn -= 4;
+                using CR = const __attribute__((address_space(4))) R;
+                CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
+                R e[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) e[k] = dp[k];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6, e[2 * k],
+                                                     e[2 * k + 1], e[2 * k + 2]);
+            }
+        } else {
+            const bool win = c >= c_win;
+            const int64_t w0 = win ? (int64_t)(c - c_win) * N : 0;
+            for (int s = 0; s < N; ++s, ++n) {
+                if (cdn == 0) {
+                    save();
+                    cdn = kc;
+                }
+                --cdn;
+                rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                                                 Dt[2 * s + 1], Dt[2 * s + 2]);
+                if (win) {
+                    const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
+                    const double U = Urow[w0 + s] * 1e9;
+                    const double e = U - u;
+                    Jn = __builtin_fma(e, e, Jn);
+                    Jd = __builtin_fma(U, U, Jd);
+                }
+            }
+        }
+        int nonfinite = !(isfinite(x) && isfinite(v));
+        nonfinite |= __shfl_xor(nonfinite, 1, 64);
+        if constexpr (G >= 4) nonfinite |= __shfl_xor(nonfinite, 2, 64);
+        if constexpr (G == 8) nonfinite |= __shfl_xor(nonfinite, 4, 64);
+        if (nonfinite) st = AFM_ST_NONFINITE;
+        else if (fabs(sample_mp<NM, COMP>(x, cx, zc, gbase)) > K.div_nm) st = AFM_ST_DIVERGED;
+    }
+    const double J = Jn / Jd;
+    if (st || !isfinite(J)) {
+        fail(st ? st : AFM_ST_NONFINITE);
+        return;
+    }
+    if (q == 0) {
+        A.J[i] = J;
+        A.status[i] = 0;
+        coef_out[i] = -2.0 / Jd;  // dJ/du_n = coef (U_n - u_n)
+    }
+}
+
 // Tangent of one slope evaluation: (dx, dv) the stage state's tangent, dz the z_c component and
 // dcv the constants' components of the column; returns the acceleration tangents.
 template <int NM, class L, typename R>
@@ -1237,8 +1374,14 @@ hipError_t launch_t(const GradArgs &a, const KConst &K, hipStream_t s) {
         if (a.form == kGradSegments && K.drive_mode == AFM_DRIVE_TABLE) {
             const int64_t nseg = ((int64_t)K.n_cycles * K.N + a.kc - 1) / a.kc;
             const int64_t lanes = a.n * nseg;
-            hipLaunchKernelGGL((k_grad_ckpt<LAW, NM, MIXED>), dim3((unsigned)((a.n + 63) / 64)),
-                               dim3(64), 0, s, a, K);
+            if (NM > 1 && a.mp) {  // one lane per mode (see k_grad_ckpt_mp)
+                constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
+                hipLaunchKernelGGL((k_grad_ckpt_mp<LAW, NM, MIXED>),
+                                   dim3((unsigned)((a.n * G + 63) / 64)), dim3(64), 0, s, a, K);
+            } else {
+                hipLaunchKernelGGL((k_grad_ckpt<LAW, NM, MIXED>),
+                                   dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, s, a, K);
+            }
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_grad_tan<LAW, NM, MIXED>), dim3((unsigned)((lanes + 255) / 256)),

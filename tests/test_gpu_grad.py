@@ -395,6 +395,35 @@ def test_grad_mode_parallel_bit_identical(afm, orc, nm):
     assert np.array_equal(rb[2][:n], ref[2])
 
 
+@pytest.mark.parametrize("nm", [2, 3, 4])
+def test_grad_segments_mode_parallel_bit_identical(afm, orc, nm):
+    """The segment form's checkpointing pass with one lane per mode (small batches) gives the
+    same checkpoints, hence the same gradient bits, as one lane per trajectory (an explicit
+    stride above 16384 points); J equals afm_misfit's."""
+    c = W.config("c5")
+    ratio = [1.0, 6.27, 17.55, 34.39][:nm]
+    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868, 0.509, -0.36][:nm]
+    m = dict(c["model"], n_modes=nm, q=[400.0] * nm, ratio=ratio, gain=gains, n_cycles=40)
+    base, free = W.full_params(c), W.free_index(c)
+    rng = np.random.default_rng(80 + nm)
+    n = 29
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), n)) if f[3] else
+                   rng.uniform(f[1], f[2], n) for f in free])
+    U = _target(orc, c, m, base)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    plan.set_grad_form("segments")
+    ref = [x.cpu().numpy() for x in plan.grad_batch(th, U[None, :], ckpt_stride=64)]
+    Jm, _ = plan.misfit(th, U[None, :])
+    assert np.array_equal(ref[0], Jm.cpu().numpy())
+    big = np.tile(th, (1, 16400 // n + 1))
+    rb = [x.cpu().numpy() for x in plan.grad_batch(big, U[None, :], ckpt_stride=64)]
+    plan.close()
+    assert np.array_equal(rb[0][:n].view(np.uint8), ref[0].view(np.uint8))
+    assert np.array_equal(rb[1][:, :n].view(np.uint8), ref[1].view(np.uint8))
+    assert np.array_equal(rb[2][:n], ref[2])
+    assert (ref[2] == 0).sum() >= n // 2
+
+
 def test_grad_eight_modes_matches_oracle_adjoint(afm, orc):
     """The paper's eight-mode beam with the Kelvin-Voigt law: mixed adjoint against the oracle's
     exact discrete adjoint (conditioning-aware tolerance), 6 points, 60 periods x 512 steps."""
