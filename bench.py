@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Published dense FP32 vector peak of MI355X, 157.3 TFLOP/s: 256 CUs x 4 SIMDs x 32 FMA lanes per
-# cycle x 2 flop x 2.4 GHz.  Measured on this build (no packed FP32 instructions): a SIMD shared by
+# cycle x 2 flop x 2.4 GHz.  Measured with the library (no packed FP32 instructions): a SIMD shared by
 # four waves completes wave-wide FP32 VALU instructions faster than one per 4 cycles (3.4 cycles
 # on average in the pixel-workload kernel, transcendentals included), so the published peak is
 # the reference; a lone wave issues at most one instruction per 4 cycles (the small-batch
@@ -700,7 +700,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the inversion path has no "
-              "multi-GPU mode in this build.", file=sys.stderr)
+              "multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
     import torch
 

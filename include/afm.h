@@ -56,7 +56,7 @@ typedef enum {
     AFM_ERR_INVALID = 1,     /* bad argument; nothing was enqueued           */
     AFM_ERR_HIP = 2,         /* HIP runtime failure (launch, copy, capture)  */
     AFM_ERR_NOMEM = 3,       /* device or host allocation failed             */
-    AFM_ERR_UNSUPPORTED = 4  /* valid request this build does not implement  */
+    AFM_ERR_UNSUPPORTED = 4  /* valid request the library does not implement */
 } afm_status;
 
 /* Arithmetic of the forward solve. */
