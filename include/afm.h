@@ -194,7 +194,11 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,
  * else 256; one lane per mode for several modes and at most 16384 trajectories, else one
  * trajectory per lane).  afm_invert tunes before it captures.  Every shape computes
- * bit-identical results.
+ * bit-identical results.  Point-mass DMT batches below 65536 trajectories run a time loop that
+ * leaves the contact force out of four-step blocks no lane of a wave can reach contact in; for
+ * 65 to 16384 trajectories their assignment to lanes follows the contact stiffness E* sqrt(R)
+ * (ranked on the device before each launch, in plan-owned buffers), which groups similar
+ * trajectories in a wave; neither changes any result.
  * block in {64, 128, 256} and tpl in {1, 2, 0} (0 = one lane per mode) pin the shape for this
  * plan (a tpl that does not apply falls back to 1); block = 0 returns to tuning.  Anything
  * else: AFM_ERR_INVALID. */
@@ -249,9 +253,12 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
  * longest period count first, taken by the waves of a grid sized to the device.  The order is
  * built on the first call for an n_cycles buffer (a synchronous read of the counts) and reused
  * while the same buffer, S and P come back (the order only balances the load: the results never
- * depend on it, so a buffer refilled with other counts still gives exact results).  The queue
- * order and counter live in a plan-owned workspace (4 (S ceil(P / 64) + 64) bytes).  Without
- * period counts: afm_misfit's tuned plain launch. */
+ * depend on it, so a buffer refilled with other counts still gives exact results).  Within each
+ * swarm the points go to lanes in the order of the force law's contact stiffness (DMT), ranked
+ * on the device before every launch; every point's result is the same whichever lane computes
+ * it.  The queue order, counter and lane order live in a plan-owned workspace
+ * (4 (S ceil(P / 64) + 64) + 12 S P bytes).  Without period counts: afm_misfit's tuned plain
+ * launch. */
 afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_t particles,
                              const double *theta, const int32_t *n_cycles,
                              const double *swarm_params, const double *targets, double *J,
