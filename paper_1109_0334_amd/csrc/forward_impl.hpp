@@ -872,7 +872,6 @@ __global__ void k_queue_reset(int32_t *head) {
 constexpr int kXcds = 8;
 constexpr int kCusPerXcd = 32;
 
-// Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
 // Lane order of a small batch: the law's contact key of every trajectory (NaN ordered last) ...
 template <int LAW>
 __global__ void __launch_bounds__(256) k_order_keys(const FwdArgs A, const KConst K) {
@@ -889,20 +888,22 @@ __global__ void __launch_bounds__(256) k_order_keys(const FwdArgs A, const KCons
 // their index order and the ranks are a permutation of 0 .. n - 1.  Keys pass through LDS in
 // tiles of the workgroup's size; every lane of a workgroup takes part in every tile.
 __global__ void __launch_bounds__(256) k_order_rank(int32_t n, const double *keys, int32_t *order) {
-    __shared__ double tile[256];
+    // the keys compared in FP32 (a coarser key only adds ties, which the index breaks)
+    __shared__ float tile[256];
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    const double ki = i < n ? keys[i] : 0.0;
+    const float ki = i < n ? (float)keys[i] : 0.0f;
     int32_t r = 0;
     for (int32_t b0 = 0; b0 < n; b0 += 256) {
         const int32_t j = b0 + (int32_t)threadIdx.x;
-        tile[threadIdx.x] = j < n ? keys[j] : INFINITY;
+        tile[threadIdx.x] = j < n ? (float)keys[j] : INFINITY;
         __syncthreads();
         // a full tile of 256: padding entries are +inf at indices >= n, above every lane's
         // index, so no padding entry is ordered before a lane
-#pragma unroll 8
+        const int32_t below = i - b0;  // tile entries k < below have a lower index than lane i
+#pragma unroll 16
         for (int32_t k = 0; k < 256; ++k) {
-            const double kj = tile[k];
-            r += (kj < ki || (kj == ki && b0 + k < i)) ? 1 : 0;
+            const float kj = tile[k];
+            r += (kj < ki || (kj == ki && k < below)) ? 1 : 0;
         }
         __syncthreads();
     }
@@ -927,6 +928,7 @@ __global__ void __launch_bounds__(256) k_order_rank_seg(int64_t n, int32_t seg, 
     order[g0 + r] = (int32_t)i;
 }
 
+// Plain launch with a given shape: `block` lanes per workgroup, `tpl` trajectories per lane.
 template <int LAW, int NM, bool MIXED>
 hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStream_t s) {
     constexpr bool branchy = Law<LAW, float>::kBranch;
