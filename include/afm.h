@@ -33,8 +33,9 @@
  *     period is not an error: its status word gets AFM_ST_NONFINITE / AFM_ST_DIVERGED, its
  *     amplitude and phase are NaN and its misfit +inf.
  *   - A plan is not thread-safe: use one plan per host thread.  Its workspaces (gradient
- *     checkpoints, polish state, inversion swarms) are reused by every call, so calls on one
- *     plan must be ordered: issue them on one stream, or synchronise between streams.
+ *     checkpoints, polish state, inversion swarms, the lane order of small batches) are reused
+ *     by every call, so calls on one plan must be ordered: issue them on one stream, or
+ *     synchronise between streams.
  */
 #ifndef AFM_H
 #define AFM_H
@@ -198,7 +199,9 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * leaves the contact force out of four-step blocks no lane of a wave can reach contact in; for
  * 65 to 16384 trajectories their assignment to lanes follows the contact stiffness E* sqrt(R)
  * (ranked on the device before each launch, in plan-owned buffers), which groups similar
- * trajectories in a wave; neither changes any result.
+ * trajectories in a wave; neither changes any result.  Batches of 65536 or more take a per-lane
+ * branch of the contact law (DMT, KV), which rounds the frozen attraction at d = a0 once ahead:
+ * their results agree with a smaller batch's to rounding, not bit for bit.
  * block in {64, 128, 256} and tpl in {1, 2, 0} (0 = one lane per mode) pin the shape for this
  * plan (a tpl that does not apply falls back to 1); block = 0 returns to tuning.  Anything
  * else: AFM_ERR_INVALID. */

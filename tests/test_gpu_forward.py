@@ -435,3 +435,64 @@ def test_misfit_swarms_work_queue(afm, orc):
         if st1[i] == 0:
             assert abs(J1[i] - o["J"]) <= PT.misfit_tol(o["J"]) or \
                 not PT.well_conditioned(orc, dict(m, n_cycles=int(ncl[i])), p)
+
+
+def test_force_forms_bit_identical(afm):
+    """The forms of the DMT contact force on the same tapping trajectories.  Three give the
+    same bits, since each adds the contact piece where a lane needs it and nothing (or an exact
+    zero) elsewhere: the work queue with more items than 4 x CUs (wave-uniform skip of the
+    contact piece per RK4 stage), the work queue with fewer (four-step blocks without it where
+    no lane can reach contact) and the plain launch below the large-batch switch (the block
+    form, lanes in contact-key order).  The plain launch above the switch takes the per-lane
+    branch, whose frozen attraction BH / a0^2 is rounded once ahead: it agrees to FP32 rounding
+    (the misfit bar), not bit for bit."""
+    import torch
+
+    c = W.config("c3")
+    m = dict(c["model"], n_cycles=60)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    P = 128
+    S = max(2 * n_cu + 6, 520)  # 2 items per swarm: more items than 4 waves per CU
+    n = S * P
+    assert n >= 65536  # the plain launch of all of them takes the per-lane branching form
+    base, free = W.full_params(c), W.free_index(c)
+    rng = np.random.default_rng(81)
+    cyc = rng.integers(20, 61, S).astype(np.int32)
+    sp = np.zeros((afm.MAX_PARAMS, S))
+    sp[: len(base)] = base[:, None]
+    sp[0] = rng.uniform(9e-9, 17e-9, S)  # 0.45 .. 0.85 A0: every swarm taps
+    N, Wn = m["steps_per_cycle"], m["lockin_cycles"] * m["steps_per_cycle"]
+    k = np.arange(1, Wn + 1)
+    U = np.stack([a * np.sin(2 * np.pi * k / N - ph)
+                  for a, ph in zip(sp[0], rng.uniform(0.5, 1.5, S))])
+    th = _theta(c, n, 82)
+    plan = afm.Plan(m, base, free, precision="mixed")
+    cyc_d = torch.tensor(cyc, device="cuda")
+    Jq, sq = (x.cpu().numpy() for x in plan.misfit_swarms(th, U, P, n_cycles=cyc_d,
+                                                           swarm_params=sp))
+    s_small = 40  # 80 items: the under-filled queue
+    Jb, sb = (x.cpu().numpy() for x in plan.misfit_swarms(
+        np.ascontiguousarray(th[:, : s_small * P]), U[:s_small], P,
+        n_cycles=cyc_d[:s_small].clone(), swarm_params=np.ascontiguousarray(sp[:, :s_small])))
+    plan_z = afm.Plan(m, base, [(0, 1e-9, 30e-9, 0)] + free, precision="mixed")
+    thz = np.vstack([np.repeat(sp[0], P)[None, :], th])
+    tid = np.repeat(np.arange(S, dtype=np.int32), P)
+    ncl = np.repeat(cyc, P)
+    Jp, stp = (x.cpu().numpy() for x in plan_z.misfit(thz, U, target_id=tid, n_cycles=ncl))
+    m_small = s_small * P
+    Js, sts = (x.cpu().numpy() for x in plan_z.misfit(
+        np.ascontiguousarray(thz[:, :m_small]), U[:s_small], target_id=tid[:m_small],
+        n_cycles=ncl[:m_small]))
+    assert (sq == 0).mean() > 0.99
+    for name, J, st in (("queue block", Jb, sb), ("plain block", Js, sts)):
+        r = slice(0, J.size)
+        assert np.array_equal(st, sq[r]), name
+        assert np.array_equal(J.view(np.uint64), Jq[r].view(np.uint64)), name
+    assert np.array_equal(stp, sq)
+    ok = sq == 0
+    rel = np.abs(Jp[ok] - Jq[ok]) / Jq[ok]
+    within = np.abs(Jp[ok] - Jq[ok]) <= PT.misfit_tol(Jq[ok])
+    print(f"per-lane branch vs skip form: {within.sum()} of {ok.sum()} within the misfit bar, "
+          f"identical bits {np.sum(Jp[ok] == Jq[ok])}, median rel {np.median(rel):.2e}, "
+          f"max rel {rel.max():.2e}")
+    assert within.mean() >= 0.99
