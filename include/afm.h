@@ -199,9 +199,11 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * leaves the contact force out of four-step blocks no lane of a wave can reach contact in; for
  * 65 to 16384 trajectories their assignment to lanes follows the contact stiffness E* sqrt(R)
  * (ranked on the device before each launch, in plan-owned buffers), which groups similar
- * trajectories in a wave; neither changes any result.  Batches of 65536 or more take a per-lane
- * branch of the contact law (DMT, KV), which rounds the frozen attraction at d = a0 once ahead:
- * their results agree with a smaller batch's to rounding, not bit for bit.
+ * trajectories in a wave; neither changes any result.  Batches of 65536 or more skip the
+ * contact piece per RK4 stage where no lane of a wave is near contact (FP32 point-mass DMT: the
+ * same bits as smaller batches) or branch per lane (FP64, and the KV law), which rounds the
+ * frozen attraction at d = a0 once ahead: those agree with a smaller batch's to rounding, not
+ * bit for bit.
  * block in {64, 128, 256} and tpl in {1, 2, 0} (0 = one lane per mode) pin the shape for this
  * plan (a tpl that does not apply falls back to 1); block = 0 returns to tuning.  Anything
  * else: AFM_ERR_INVALID. */

@@ -438,14 +438,12 @@ def test_misfit_swarms_work_queue(afm, orc):
 
 
 def test_force_forms_bit_identical(afm):
-    """The forms of the DMT contact force on the same tapping trajectories.  Three give the
-    same bits, since each adds the contact piece where a lane needs it and nothing (or an exact
-    zero) elsewhere: the work queue with more items than 4 x CUs (wave-uniform skip of the
-    contact piece per RK4 stage), the work queue with fewer (four-step blocks without it where
-    no lane can reach contact) and the plain launch below the large-batch switch (the block
-    form, lanes in contact-key order).  The plain launch above the switch takes the per-lane
-    branch, whose frozen attraction BH / a0^2 is rounded once ahead: it agrees to FP32 rounding
-    (the misfit bar), not bit for bit."""
+    """The forms of the FP32 DMT contact force give the same bits on the same tapping
+    trajectories, since each adds the contact piece where a lane needs it and nothing (or an
+    exact zero) elsewhere: the work queue with more items than 4 x CUs (wave-uniform skip of the
+    contact piece per RK4 stage) and with fewer (four-step blocks without it where no lane can
+    reach contact), the plain launch above the large-batch switch (the per-stage skip) and below
+    it (the block form, lanes in contact-key order)."""
     import torch
 
     c = W.config("c3")
@@ -484,15 +482,8 @@ def test_force_forms_bit_identical(afm):
         np.ascontiguousarray(thz[:, :m_small]), U[:s_small], target_id=tid[:m_small],
         n_cycles=ncl[:m_small]))
     assert (sq == 0).mean() > 0.99
-    for name, J, st in (("queue block", Jb, sb), ("plain block", Js, sts)):
+    for name, J, st in (("plain large", Jp, stp), ("queue block", Jb, sb),
+                        ("plain block", Js, sts)):
         r = slice(0, J.size)
         assert np.array_equal(st, sq[r]), name
         assert np.array_equal(J.view(np.uint64), Jq[r].view(np.uint64)), name
-    assert np.array_equal(stp, sq)
-    ok = sq == 0
-    rel = np.abs(Jp[ok] - Jq[ok]) / Jq[ok]
-    within = np.abs(Jp[ok] - Jq[ok]) <= PT.misfit_tol(Jq[ok])
-    print(f"per-lane branch vs skip form: {within.sum()} of {ok.sum()} within the misfit bar, "
-          f"identical bits {np.sum(Jp[ok] == Jq[ok])}, median rel {np.median(rel):.2e}, "
-          f"max rel {rel.max():.2e}")
-    assert within.mean() >= 0.99
