@@ -107,12 +107,13 @@ def lib() -> C.CDLL:
     L.afm_beam_shapes.argtypes = [i32, i32, vp, vp]
     L.afm_forward_points.argtypes = [vp, i64, vp, vp, i32, vp, vp, vp, vp, vp, vp]
     L.afm_forward_steady.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.afm_misfit_swarms.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     L.afm_last_error.restype = C.c_char_p
     L.afm_version.restype = C.c_char_p
     for f in ("afm_plan_create", "afm_plan_destroy", "afm_forward_batch", "afm_misfit",
               "afm_grad_batch", "afm_grad_batch_noalloc", "afm_polish", "afm_swarm_init", "afm_pso_step", "afm_invert",
               "afm_beam_modes", "afm_beam_shapes", "afm_forward_points", "afm_forward_steady",
-              "afm_separations"):
+              "afm_separations", "afm_misfit_swarms"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L

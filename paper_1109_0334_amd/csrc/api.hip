@@ -352,7 +352,7 @@ static afm_status check_swarm(const afm_plan *plan, const afm_swarm *sw) {
     if (sw->n_dim != plan->prob.n_free || sw->n_dim < 1)
         return fail(AFM_ERR_INVALID, "swarm n_dim must equal the problem's n_free (>= 1)");
     if (sw->particles < 1 || sw->swarms < 1) return fail(AFM_ERR_INVALID, "particles and swarms must be >= 1");
-    if ((int64_t)sw->particles * sw->swarms > (int64_t)1 << 31)
+    if ((int64_t)sw->particles * sw->swarms > INT32_MAX)
         return fail(AFM_ERR_INVALID, "swarm too large");
     if (!sw->z || !sw->v || !sw->pbest_z || !sw->pbest_J || !sw->gbest_z || !sw->gbest_J ||
         !sw->gen_to_cutoff || !sw->theta)

@@ -113,7 +113,7 @@ extern "C" afm_status afm_invert(afm_plan *plan, int32_t n_swarms, const double 
     if (D < 1) return fail(AFM_ERR_INVALID, "the problem has no free parameters");
     if (n_swarms < 1 || particles < 1 || iters < 1)
         return fail(AFM_ERR_INVALID, "n_swarms, particles and iters must be >= 1");
-    if ((int64_t)n_swarms * particles > (int64_t)1 << 31) return fail(AFM_ERR_INVALID, "swarm too large");
+    if ((int64_t)n_swarms * particles > INT32_MAX) return fail(AFM_ERR_INVALID, "swarm too large");
     if (!targets || !best_theta || !best_J || !gen_to_cutoff)
         return fail(AFM_ERR_INVALID, "targets and outputs are required");
     if (lbfgs_steps < 0 || lbfgs_topk < 0 || lbfgs_topk > particles)
@@ -273,7 +273,7 @@ extern "C" afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_
                                         double *J, int32_t *status, afm_stream_t stream) {
     if (!plan) return fail(AFM_ERR_INVALID, "plan is NULL");
     if (n_swarms < 0 || particles < 1) return fail(AFM_ERR_INVALID, "need n_swarms >= 0 and particles >= 1");
-    if ((int64_t)n_swarms * particles > (int64_t)1 << 31) return fail(AFM_ERR_INVALID, "batch too large");
+    if ((int64_t)n_swarms * particles > INT32_MAX) return fail(AFM_ERR_INVALID, "batch too large");
     if (n_swarms == 0) return AFM_OK;
     if ((plan->prob.n_free > 0 && !theta) || !targets || !J || !status)
         return fail(AFM_ERR_INVALID, "theta, targets, J and status are required");

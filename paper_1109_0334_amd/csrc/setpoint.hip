@@ -122,7 +122,7 @@ extern "C" afm_status afm_separations(afm_plan *plan, int32_t n_pixels, const do
     if (K < 2 || K > 100000) return fail(AFM_ERR_INVALID, "afm_separations: step gives too few or too many grid points");
     const int64_t S = n_pixels;
     const int64_t n_grid = S * K, n_max = std::max<int64_t>(n_grid, S * kSections);
-    if (n_max > ((int64_t)1 << 31)) return fail(AFM_ERR_INVALID, "afm_separations: too many pixels");
+    if (n_max > INT32_MAX) return fail(AFM_ERR_INVALID, "afm_separations: too many pixels");
 
     // the amplitude solves: the plan's problem in FP64 over `periods` periods, z_c the one free
     // parameter, every other parameter from the pixel's vector

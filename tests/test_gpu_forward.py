@@ -487,3 +487,24 @@ def test_force_forms_bit_identical(afm):
         r = slice(0, J.size)
         assert np.array_equal(st, sq[r]), name
         assert np.array_equal(J.view(np.uint64), Jq[r].view(np.uint64)), name
+
+
+def test_int32_batch_limits_are_refused(afm):
+    """Swarm batches index their points with 32-bit integers: 2^31 points (one more than an
+    int32 holds) are refused with AFM_ERR_INVALID before any pointer is read or anything is
+    enqueued, by afm_misfit_swarms, afm_invert and afm_swarm_init alike."""
+    import ctypes as C
+
+    c = W.config("c2")
+    plan = _plan(afm, c, "mixed", model=dict(c["model"], n_cycles=40))
+    L = afm.lib()
+    S, P = 1 << 16, 1 << 15
+    assert L.afm_misfit_swarms(plan._h, S, P, None, None, None, None, None, None, None) == 1
+    assert b"too large" in L.afm_last_error()
+    assert L.afm_invert(plan._h, S, None, None, None, P, 1, 0, 0.0, 0, 0, None, None, None,
+                        None) == 1
+    assert b"too large" in L.afm_last_error()
+    sw = afm._Swarm(n_dim=plan.n_free, particles=P, swarms=S)
+    assert L.afm_swarm_init(plan._h, C.byref(sw), 0, None) == 1
+    assert b"too large" in L.afm_last_error()
+    plan.close()
