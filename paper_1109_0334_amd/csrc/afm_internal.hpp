@@ -667,8 +667,8 @@ hipError_t launch_gather_best(const afm_plan *plan, const afm_swarm &sw, double 
 hipError_t launch_grad(const afm_plan *plan, const GradArgs &a, hipStream_t s);
 hipError_t launch_grad_p(const afm_plan *plan, int32_t prec, const GradArgs &a, hipStream_t s);
 hipError_t launch_forward_p(const afm_plan *plan, int32_t prec, const FwdArgs &a, hipStream_t s);
-// Batches at and above this many trajectories are treated as GPU-filling (four-wave blocks,
-// per-lane branching force law); below it one wave owns a SIMD.
+// Batches at and above this many trajectories are treated as GPU-filling (256-lane workgroups,
+// the force-law forms of throughput-bound launches); below it one wave owns a SIMD.
 constexpr int64_t kSmallBatch = 65536;
 // largest small batch whose lanes are ordered by the law's contact key (see launch_plain)
 constexpr int64_t kOrderMax = 16384;

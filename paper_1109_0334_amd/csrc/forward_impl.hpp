@@ -860,9 +860,10 @@ __global__ void k_queue_reset(int32_t *head) {
 
 // Force-law form by regime (not tuned: the per-lane branching form rounds the in-contact
 // attraction differently, and tuning must never change results).  Small batches (fewer waves
-// than SIMDs) are issue-latency bound: the branch-free form needs the fewest issue slots.  Large
-// batches are throughput bound: the per-lane branch (fewer transcendental ops; other waves
-// hide its scalar instructions).
+// than SIMDs) are issue-latency bound: the branch-free form (with the block-level test for a
+// point mass) needs the fewest issue slots.  Large batches are throughput bound: the per-stage
+// skip for FP32 point-mass DMT (the small batches' bits), else the per-lane branch (fewer
+// transcendental ops; other waves hide its scalar instructions).
 
 // Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8), each XCD with its
 // own L2 and 32 CUs.  A launch of at most 32 workgroups is issue-latency bound on as many CUs
