@@ -195,11 +195,12 @@ afm_status afm_plan_destroy(afm_plan *plan);
  * capture nothing is timed and the default shape is used (64 lanes below 65536 trajectories,
  * else 256; one lane per mode for several modes and at most 16384 trajectories, else one
  * trajectory per lane).  afm_invert tunes before it captures.  Every shape computes
- * bit-identical results.  Point-mass DMT batches below 65536 trajectories run a time loop that
- * leaves the contact force out of four-step blocks no lane of a wave can reach contact in; for
- * 65 to 16384 trajectories their assignment to lanes follows the contact stiffness E* sqrt(R)
- * (ranked on the device before each launch, in plan-owned buffers), which groups similar
- * trajectories in a wave; neither changes any result.  Batches of 65536 or more skip the
+ * bit-identical results.  DMT and Kelvin-Voigt batches below 65536 trajectories (one lane per
+ * trajectory or per mode) run a time loop that leaves the contact force out of four-step blocks
+ * no lane of a wave can reach contact in; for point-mass batches of 65 to 16384 trajectories
+ * their assignment to lanes follows the contact stiffness E* sqrt(R) (ranked on the device
+ * before each launch, in plan-owned buffers), which groups similar trajectories in a wave;
+ * neither changes any result.  Batches of 65536 or more skip the
  * contact piece per RK4 stage where no lane of a wave is near contact (FP32 point-mass DMT: the
  * same bits as smaller batches) or branch per lane (FP64, and the KV law), which rounds the
  * frozen attraction at d = a0 once ahead: those agree with a smaller batch's to rounding, not

@@ -339,7 +339,7 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
     // FP32 form of the contact piece as for DMT: with q = ce (a0 - d) clamped by a median
     // (ce = sgn(BE) |BE|^{2/3}, |ce| >= 1e-30 so that E* = 0 stays finite), the Hertz and
     // viscous terms are sqrt(|q|) (q + BVs d') with BVs = BV / sqrt(|ce|).
-    R zc, a0, BH, BHa, BE, BV, ce, cea0, clim, BVs;
+    R zc, a0, BH, BHa, BE, BV, ce, cea0, clim, BVs, dskip, fmax;
     Law() = default;
     __device__ Law(const double *p, const KConst &K) {
         const double a0n = p[3] * 1e9;
@@ -358,9 +358,31 @@ template <typename R> struct Law<AFM_LAW_KV, R> {
         cea0 = (R)(c * a0n);
         clim = be < 0.0 ? -(R)INFINITY : (R)INFINITY;
         BVs = (R)(bv / ::sqrt(m));
+        // the block test's threshold and largest out-of-contact attraction, as for DMT (the
+        // viscous term, like the Hertz term, vanishes with q)
+        dskip = (R)(a0n + ::fabs(a0n) * 0x1p-20);
+        const double ds = (double)dskip;
+        fmax = ds > 0.0 ? (R)(::fabs(bh) / (ds * ds) * (1.0 + 1e-6)) : (R)INFINITY;
+    }
+    // kFmBlock: out of contact the law is DMT's far field, so DMT's block bound holds
+    static constexpr bool kBlock = true;
+    __host__ __device__ static double contact_key(const double *p) {
+        return p[2] * ::sqrt(::fabs(p[4]));
+    }
+    __device__ inline bool near(R g, R v, const BlockBound<R> &bb) const {
+        const R av = Ops<R>::abs(v);
+        const R Am = Ops<R>::fma(bb.c_u, Ops<R>::abs(g - zc),
+                                 Ops<R>::fma(bb.c_v, av, Ops<R>::fma(bb.c_f, fmax, bb.c_0)));
+        const R reach = Ops<R>::fma(bb.h4, Ops<R>::max(Ops<R>::fma(bb.h16, Am, -v), R(0)), R(1e-3));
+        return !(g - reach > dskip);
     }
     template <int FM> __device__ inline R add(R d, R dd, R b) const {
-        if constexpr (std::is_same<R, float>::value) {
+        if constexpr (FM == kFmFar) {
+            // only where every stage gap is at least dskip > a0 (the block bound): q = 0 there,
+            // and the branch-free form adds sqrt(0) (q + BVs d') = an exact zero
+            const R r = Ops<R>::rcp(d);
+            return Ops<R>::fma(BH * r, r, b);
+        } else if constexpr (std::is_same<R, float>::value) {
             if constexpr (FM != kFmBranch) {
                 const R r = Ops<R>::rcp(__builtin_amdgcn_fmed3f(d, a0, R(3.4028234663852886e38)));
                 const R q = __builtin_amdgcn_fmed3f(Ops<R>::fma(-ce, d, cea0), R(0), clim);

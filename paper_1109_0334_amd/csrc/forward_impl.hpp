@@ -440,6 +440,10 @@ __device__ __forceinline__ LaneOut integrate_mp(
     using R = typename std::conditional<MIXED, float, double>::type;
     constexpr bool COMP = MIXED;
     constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
+    // kFmBlock: the four-step blocks of the transient test a bound once per block (a law that
+    // has one); every other loop uses the branch-free form, which adds the same terms
+    constexpr bool BLK = FM == kFmBlock && !DP && HasBlock<Law<LAW, R>>::value;
+    constexpr int FS = FM == kFmBlock ? kFmFree : FM;
     const R *__restrict__ Dt;
     if constexpr (MIXED) Dt = K.drive_f;
     else Dt = K.drive_d;
@@ -448,6 +452,11 @@ __device__ __forceinline__ LaneOut integrate_mp(
 
     ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
     R x = R(0), v = R(0), cx = R(0), cv = R(0);
+    // this lane's share of the block bound (the point mass's BlockBound per mode, summed over
+    // the group): its mode's acceleration stays within bu |x - zoff| + bv |v| + bf fmax + b0
+    // during a block, and the gap's within the group sum; zero for a lane without a mode; a
+    // mode too fast for the bound at this step (denominator below 0.2) disables the skip
+    R bu = R(0), bvv = R(0), bf = R(0), b0 = R(0);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         if (q == i) {
@@ -458,8 +467,22 @@ __device__ __forceinline__ LaneOut integrate_mp(
             ml.w = R(1);
             x = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
             v = (R)K.y0[NM + i];
+            if constexpr (BLK) {
+                const double hh = K.h, o2 = K.om2[i], c = K.cdamp[i];
+                const double den = 1.0 - 16.0 * hh * hh * o2 - 4.0 * hh * c;
+                const double qf = den >= 0.2 ? 1.02 / den : 0.0;
+                bu = (R)(o2 * qf);
+                bvv = (R)((4.0 * hh * o2 + c) * qf);
+                bf = (R)qf;
+                b0 = den >= 0.2 ? (R)(::fabs(K.gain[i]) * K.dmax * qf) : (R)INFINITY;
+            }
         }
     }
+    const R bh4 = (R)(4.0 * K.h * 1.02);
+    bool bound_ok = BLK;  // every mode slow enough for the bound (uniform: the plan's modes)
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        bound_ok = bound_ok && 1.0 - 16.0 * K.h * K.h * K.om2[i] - 4.0 * K.h * K.cdamp[i] >= 0.2;
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     const int N = K.N;
     const int c_win = nc - K.lockin;
@@ -487,16 +510,16 @@ __device__ __forceinline__ LaneOut integrate_mp(
             for (; s + 4 <= N; s += 4) {
                 R d[8];
                 drive8(jb + 2.0 * s + 1.0, d);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dc, d[0], d[1]);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[1], d[2], d[3]);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[3], d[4], d[5]);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, d[5], d[6], d[7]);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, Dc, d[0], d[1]);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, d[1], d[2], d[3]);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, d[3], d[4], d[5]);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, d[5], d[6], d[7]);
                 Dc = d[7];
             }
             for (; s < N; ++s) {
                 const double j = jb + 2.0 * s;
                 const R D1 = dv.at(j + 1.0), D2 = dv.at(j + 2.0);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dc, D1, D2);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, Dc, D1, D2);
                 Dc = D2;
             }
         } else if (c < c_win) {
@@ -506,13 +529,34 @@ __device__ __forceinline__ LaneOut integrate_mp(
                 CR *dp = (CR *)(Dt + __builtin_amdgcn_readfirstlane(2 * s));
                 const R e0 = dp[0], e1 = dp[1], e2 = dp[2], e3 = dp[3], e4 = dp[4], e5 = dp[5],
                         e6 = dp[6], e7 = dp[7], e8 = dp[8];
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e0, e1, e2);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e2, e3, e4);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e4, e5, e6);
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, e6, e7, e8);
+                auto block = [&](auto fm_tag) {
+                    constexpr int F = decltype(fm_tag)::value;
+                    rk4_step_mp<NM, G, COMP, F>(law, ml, x, v, cx, cv, h, h2, h6, e0, e1, e2);
+                    rk4_step_mp<NM, G, COMP, F>(law, ml, x, v, cx, cv, h, h2, h6, e2, e3, e4);
+                    rk4_step_mp<NM, G, COMP, F>(law, ml, x, v, cx, cv, h, h2, h6, e4, e5, e6);
+                    rk4_step_mp<NM, G, COMP, F>(law, ml, x, v, cx, cv, h, h2, h6, e6, e7, e8);
+                };
+                bool far = false;
+                if constexpr (BLK) {
+                    if (bound_ok) {
+                        // the gap g and its rate fall by at most 4h max(0, 4h A* - v) within
+                        // the block, A* the group sum of the modes' acceleration bounds (every
+                        // stage of every mode takes the same RK4 weights), as for the point mass
+                        const R Tq = Ops<R>::fma(bu, Ops<R>::abs(x - ml.zoff),
+                                                 Ops<R>::fma(bvv, Ops<R>::abs(v),
+                                                             Ops<R>::fma(bf, law.fmax, b0)));
+                        const R Am = group_sum<G>(Tq);
+                        const R g = group_sum<G>(x), vg = group_sum<G>(v);
+                        const R reach = Ops<R>::fma(
+                            bh4, Ops<R>::max(Ops<R>::fma(bh4, Am, -vg), R(0)), R(1e-3));
+                        far = __builtin_amdgcn_ballot_w64(!(g - reach > law.dskip)) == 0;
+                    }
+                }
+                if (far) block(std::integral_constant<int, kFmFar>());
+                else block(std::integral_constant<int, FS>());
             }
             for (; s < N; ++s)
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, Dt[2 * s],
                                              Dt[2 * s + 1], Dt[2 * s + 2]);
         } else {
             const int w0 = (c - c_win) * N;
@@ -525,7 +569,7 @@ __device__ __forceinline__ LaneOut integrate_mp(
                 constexpr bool OUT = decltype(out_tag)::value;
                 const double Uc = Un;
                 if (Up) Un = Up[s + 1 < N ? s + 1 : s];
-                rk4_step_mp<NM, G, COMP, FM>(law, ml, x, v, cx, cv, h, h2, h6, D0, D1, D2);
+                rk4_step_mp<NM, G, COMP, FS>(law, ml, x, v, cx, cv, h, h2, h6, D0, D1, D2);
                 const double u = sample_mp<NM, COMP>(x, cx, zc, gbase);
                 Sc = __builtin_fma(u, Lc[s + 1], Sc);
                 Ss = __builtin_fma(u, Ls[s + 1], Ss);
@@ -938,8 +982,7 @@ hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStre
     // contact (the bits of the smaller batches' forms; 257 vs 294 ms for the per-lane branch on
     // 524,288 pixel trajectories of 100-2000 periods, 9.3 vs 9.1 ms on a 40-period batch that
     // is all transient); the other laws with a contact branch, and FP64, branch per lane
-    constexpr int kLargeFm = MIXED && NM == 1 && HasBlock<Law<LAW, float>>::value ? kFmSkip
-                                                                                  : kFmBranch;
+    constexpr int kLargeFm = MIXED && NM == 1 && LAW == AFM_LAW_DMT ? kFmSkip : kFmBranch;
     const dim3 blk((unsigned)sh.block);
     const bool large = branchy && a0.n >= kSmallBatch;
     if constexpr (NM > 1) {
@@ -947,8 +990,13 @@ hipError_t launch_plain(const FwdArgs &a0, const KConst &K, FwdShape sh, hipStre
             constexpr int G = NM <= 2 ? 2 : (NM <= 4 ? 4 : 8);
             const int64_t per = sh.block / G;
             const dim3 g2((unsigned)((a0.n + per - 1) / per));
+            // small batches: the block-level contact test where the law has a bound
+            constexpr int kMpFm =
+                HasBlock<Law<LAW, typename std::conditional<MIXED, float, double>::type>>::value
+                    ? kFmBlock
+                    : kFmFree;
             if (large) hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmBranch>), g2, blk, 0, s, a0, K);
-            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kFmFree>), g2, blk, 0, s, a0, K);
+            else hipLaunchKernelGGL((k_forward_mp<LAW, NM, MIXED, kMpFm>), g2, blk, 0, s, a0, K);
             return hipGetLastError();
         }
     }
