@@ -508,3 +508,39 @@ def test_int32_batch_limits_are_refused(afm):
     assert L.afm_swarm_init(plan._h, C.byref(sw), 0, None) == 1
     assert b"too large" in L.afm_last_error()
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_kv_point_mass_block_form(afm, orc, precision):
+    """Point-mass Kelvin-Voigt batches of 65 to 16384 trajectories run the block-level contact
+    test with lanes in contact-key order: their misfits equal those of the gradient's forward
+    pass (the branch-free form) bit for bit, a permuted batch permutes them bit for bit, and
+    sampled points match the oracle."""
+    import torch
+
+    c = W.config("c2")
+    m = dict(c["model"], law="kv", n_cycles=80)
+    base = np.append(W.full_params(c), 10.0)  # (z_c, H, E*, a0, R) of c2, eta = 10 Pa s
+    free = [(1, 1e-20, 1e-19, 0), (2, 0.1e9, 10e9, 1), (5, 1.0, 100.0, 1)]
+    n = 1000
+    rng = np.random.default_rng(91)
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), n)) if f[3] else
+                   rng.uniform(f[1], f[2], n) for f in free])
+    U = orc.forward(m, base, want_trace=True)["trace"]
+    plan = afm.Plan(m, base, free, precision=precision)
+    thd = torch.tensor(th, device="cuda")
+    J, st = (x.cpu().numpy() for x in plan.misfit(thd, U[None, :]))
+    Jg, _, stg = (x.cpu().numpy() for x in plan.grad_batch(thd, U[None, :]))
+    assert np.array_equal(st, stg) and (st == 0).mean() > 0.95
+    assert np.array_equal(J.view(np.uint64), Jg.view(np.uint64))
+    perm = rng.permutation(n)
+    Jp = plan.misfit(torch.tensor(np.ascontiguousarray(th[:, perm]), device="cuda"),
+                     U[None, :])[0].cpu().numpy()
+    assert np.array_equal(J[perm].view(np.uint64), Jp.view(np.uint64))
+    idx = rng.choice(n, 8, replace=False)
+    P = PT.full_from_free(base, free, th[:, idx])
+    o = PT.oracle_batch(orc, m, P, target=U)
+    tol = (lambda Jo: 1e-9 * Jo + 1e-15) if precision == "fp64" else PT.misfit_tol
+    assert np.array_equal(st[idx], o["status"])
+    for k in np.flatnonzero(np.abs(J[idx] - o["J"]) > tol(o["J"])):
+        assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
