@@ -260,9 +260,9 @@ afm_status afm_misfit(afm_plan *plan, int64_t n, const double *theta, const int3
  * built on the first call for an n_cycles buffer (a synchronous read of the counts) and reused
  * while the same buffer, S and P come back (the order only balances the load: the results never
  * depend on it, so a buffer refilled with other counts still gives exact results).  Within each
- * swarm the points go to lanes in the order of the force law's contact stiffness (DMT, Kelvin-Voigt), ranked
- * on the device before every launch; every point's result is the same whichever lane computes
- * it.  The queue order, counter and lane order live in a plan-owned workspace
+ * swarm the points go to lanes in the order of the force law's contact stiffness (DMT,
+ * Kelvin-Voigt), ranked on the device before every launch; every point's result is the same
+ * whichever lane computes it.  The queue order, counter and lane order live in a plan-owned workspace
  * (4 (S ceil(P / 64) + 64) + 12 S P bytes).  Without period counts: afm_misfit's tuned plain
  * launch. */
 afm_status afm_misfit_swarms(afm_plan *plan, int32_t n_swarms, int32_t particles,
