@@ -544,3 +544,32 @@ def test_kv_point_mass_block_form(afm, orc, precision):
     assert np.array_equal(st[idx], o["status"])
     for k in np.flatnonzero(np.abs(J[idx] - o["J"]) > tol(o["J"])):
         assert precision == "mixed" and not PT.well_conditioned(orc, m, P[k])
+
+
+@pytest.mark.parametrize("nm,law", [(2, "dmt"), (3, "kv")])
+def test_mode_parallel_block_form_fp64(afm, nm, law):
+    """FP64 mode-parallel batches run the block-level contact test too: one lane per mode gives
+    the bits of one lane per trajectory (the branch-free form) on tapping trajectories."""
+    import torch
+
+    c = W.config("c5")
+    ratio = [1.0, 6.27, 17.55][:nm]
+    gains = c["model"]["gain"] if nm == 3 else [1.566, -0.868]
+    m = dict(c["model"], law=law, n_modes=nm, q=[400.0] * nm, ratio=ratio, gain=gains,
+             n_cycles=40)
+    npar = 5 if law == "dmt" else 6
+    base = W.full_params(c)[:npar]
+    free = [f for f in W.free_index(c) if f[0] < npar]
+    rng = np.random.default_rng(60 + nm)
+    n = 200
+    th = np.stack([np.exp(rng.uniform(np.log(f[1]), np.log(f[2]), n)) if f[3] else
+                   rng.uniform(f[1], f[2], n) for f in free])
+    plan = afm.Plan(m, base, free, precision="fp64")
+    thd = torch.tensor(th, device="cuda")
+    plan.set_launch_shape(64, 1)
+    ref = {k: v.cpu().numpy() for k, v in plan.forward_batch(thd).items() if v is not None}
+    assert (ref["status"] == 0).mean() > 0.9
+    plan.set_launch_shape(64, 0)
+    r = {k: v.cpu().numpy() for k, v in plan.forward_batch(thd).items() if v is not None}
+    for k in ref:
+        assert np.array_equal(r[k].view(np.uint8), ref[k].view(np.uint8)), k
