@@ -452,11 +452,6 @@ __device__ __forceinline__ LaneOut integrate_mp(
 
     ModeLane<R> ml{R(0), R(0), R(0), R(0), R(0)};
     R x = R(0), v = R(0), cx = R(0), cv = R(0);
-    // this lane's share of the block bound (the point mass's BlockBound per mode, summed over
-    // the group): its mode's acceleration stays within bu |x - zoff| + bv |v| + bf fmax + b0
-    // during a block, and the gap's within the group sum; zero for a lane without a mode; a
-    // mode too fast for the bound at this step (denominator below 0.2) disables the skip
-    R bu = R(0), bvv = R(0), bf = R(0), b0 = R(0);
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
         if (q == i) {
@@ -467,22 +462,9 @@ __device__ __forceinline__ LaneOut integrate_mp(
             ml.w = R(1);
             x = (R)(i == 0 ? zc + K.y0[0] : K.y0[i]);
             v = (R)K.y0[NM + i];
-            if constexpr (BLK) {
-                const double hh = K.h, o2 = K.om2[i], c = K.cdamp[i];
-                const double den = 1.0 - 16.0 * hh * hh * o2 - 4.0 * hh * c;
-                const double qf = den >= 0.2 ? 1.02 / den : 0.0;
-                bu = (R)(o2 * qf);
-                bvv = (R)((4.0 * hh * o2 + c) * qf);
-                bf = (R)qf;
-                b0 = den >= 0.2 ? (R)(::fabs(K.gain[i]) * K.dmax * qf) : (R)INFINITY;
-            }
         }
     }
-    const R bh4 = (R)(4.0 * K.h * 1.02);
-    bool bound_ok = BLK;  // every mode slow enough for the bound (uniform: the plan's modes)
-#pragma unroll
-    for (int i = 0; i < NM; ++i)
-        bound_ok = bound_ok && 1.0 - 16.0 * K.h * K.h * K.om2[i] - 4.0 * K.h * K.cdamp[i] >= 0.2;
+    const ModeBound<R> mb(K, NM, q);  // this lane's share of the block bound
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
     const int N = K.N;
     const int c_win = nc - K.lockin;
@@ -537,21 +519,7 @@ __device__ __forceinline__ LaneOut integrate_mp(
                     rk4_step_mp<NM, G, COMP, F>(law, ml, x, v, cx, cv, h, h2, h6, e6, e7, e8);
                 };
                 bool far = false;
-                if constexpr (BLK) {
-                    if (bound_ok) {
-                        // the gap g and its rate fall by at most 4h max(0, 4h A* - v) within
-                        // the block, A* the group sum of the modes' acceleration bounds (every
-                        // stage of every mode takes the same RK4 weights), as for the point mass
-                        const R Tq = Ops<R>::fma(bu, Ops<R>::abs(x - ml.zoff),
-                                                 Ops<R>::fma(bvv, Ops<R>::abs(v),
-                                                             Ops<R>::fma(bf, law.fmax, b0)));
-                        const R Am = group_sum<G>(Tq);
-                        const R g = group_sum<G>(x), vg = group_sum<G>(v);
-                        const R reach = Ops<R>::fma(
-                            bh4, Ops<R>::max(Ops<R>::fma(bh4, Am, -vg), R(0)), R(1e-3));
-                        far = __builtin_amdgcn_ballot_w64(!(g - reach > law.dskip)) == 0;
-                    }
-                }
+                if constexpr (BLK) far = group_far<G>(law, ml, mb, x, v);
                 if (far) block(std::integral_constant<int, kFmFar>());
                 else block(std::integral_constant<int, FS>());
             }

@@ -948,6 +948,9 @@ __global__ void __launch_bounds__(64) k_grad_ckpt_mp(const GradArgs A, const KCo
         }
     }
     const R h = (R)K.h, h2 = (R)(0.5 * K.h), h6 = (R)(K.h / 6.0);
+    // the forward's block-level contact test (laws with a bound): far blocks without the
+    // contact piece, which adds exact zeros there, so the checkpoints keep their bits
+    const ModeBound<R> mb(K, NM, q);
     float *__restrict__ ck = A.ckpt;
     double Jn = 0.0, Jd = 0.0;
     int32_t st = 0;
@@ -982,10 +985,19 @@ __global__ void __launch_bounds__(64) k_grad_ckpt_mp(const GradArgs A, const KCo
                 R e[9];
 #pragma unroll
                 for (int k = 0; k < 9; ++k) e[k] = dp[k];
+                bool far = false;
+                if constexpr (HasBlock<L>::value) far = group_far<G>(law, ml, mb, x, v);
+                if (far) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6, e[2 * k],
-                                                     e[2 * k + 1], e[2 * k + 2]);
+                    for (int k = 0; k < 4; ++k)
+                        rk4_step_mp<NM, G, COMP, kFmFar>(law, ml, x, v, cx, cv, h, h2, h6,
+                                                        e[2 * k], e[2 * k + 1], e[2 * k + 2]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        rk4_step_mp<NM, G, COMP, kFmFree>(law, ml, x, v, cx, cv, h, h2, h6,
+                                                         e[2 * k], e[2 * k + 1], e[2 * k + 2]);
+                }
             }
         } else {
             const bool win = c >= c_win;

@@ -240,6 +240,50 @@ struct ModeLane {
     R om2, cd, gn, zoff, w;
 };
 
+// The block-level contact test of a mode-parallel group (the point mass's BlockBound, mode by
+// mode): over a block of four steps the acceleration of mode q stays within
+// u |x_q - zoff| + v |v_q| + f fmax + c0, with u, v, f, c0 the point-mass coefficients of its
+// frequency, damping and drive gain; the group sum of these bounds bounds the gap's, and since
+// every stage of every mode takes the same RK4 weights, no stage gap falls below
+// g - 4h max(0, 4h A* - g') (g, g' the gap and its rate).  A lane without a mode has zero
+// coefficients.  ok is false, for every lane, when some mode is too fast for the bound at this
+// step (denominator below 0.2): then the test always answers "near".
+template <typename R>
+struct ModeBound {
+    R u = R(0), v = R(0), f = R(0), c0 = R(0), h4 = R(0);
+    bool ok = false;
+    __device__ ModeBound(const KConst &K, int nm, int q) {
+        const double hh = K.h;
+        ok = true;
+        for (int i = 0; i < nm; ++i)
+            ok = ok && 1.0 - 16.0 * hh * hh * K.om2[i] - 4.0 * hh * K.cdamp[i] >= 0.2;
+        h4 = (R)(4.0 * hh * 1.02);
+        if (q < nm) {
+            const double o2 = K.om2[q], c = K.cdamp[q];
+            const double den = 1.0 - 16.0 * hh * hh * o2 - 4.0 * hh * c;
+            const double qf = den >= 0.2 ? 1.02 / den : 0.0;
+            u = (R)(o2 * qf);
+            v = (R)((4.0 * hh * o2 + c) * qf);
+            f = (R)qf;
+            c0 = den >= 0.2 ? (R)(::fabs(K.gain[q]) * K.dmax * qf) : (R)INFINITY;
+        }
+    }
+};
+
+// Whether no group of the wave can come within the law's dskip of contact during the next four
+// steps (wave-uniform).  NaN states count as near.
+template <int G, typename R, class L>
+__device__ __forceinline__ bool group_far(const L &law, const ModeLane<R> &ml,
+                                          const ModeBound<R> &mb, R x, R v) {
+    if (!mb.ok) return false;
+    const R Tq = Ops<R>::fma(mb.u, Ops<R>::abs(x - ml.zoff),
+                             Ops<R>::fma(mb.v, Ops<R>::abs(v), Ops<R>::fma(mb.f, law.fmax, mb.c0)));
+    const R Am = group_sum<G>(Tq);
+    const R g = group_sum<G>(x), vg = group_sum<G>(v);
+    const R reach = Ops<R>::fma(mb.h4, Ops<R>::max(Ops<R>::fma(mb.h4, Am, -vg), R(0)), R(1e-3));
+    return __builtin_amdgcn_ballot_w64(!(g - reach > law.dskip)) == 0;
+}
+
 template <int NM, int G, int FM, typename R, class L>
 __device__ __forceinline__ R accel_mp(const L &law, const ModeLane<R> &ml, R x, R v, R D) {
     const R d = group_sum<G>(x);
